@@ -1,0 +1,92 @@
+"""Checks that pin the oracle to facts the paper and the mathematics fix.
+
+Each function returns the largest violation it finds, so that a test can
+assert both that the oracle passes and that a planted mistake does not.
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def read_poisson_table():
+    """Rows of tests/golden/poisson2d_iterations.txt as {(table, t): [counts]}."""
+    out = {}
+    with open(os.path.join(GOLDEN, "poisson2d_iterations.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            parts = line.split()
+            out[(parts[0], int(parts[1]))] = [int(v) for v in parts[2:]]
+    return out
+
+
+SVALS = [1, 2, 3, 4, 5, 8, 10]
+
+
+def orthonormality_violation(res, A) -> float:
+    """max_k ||V_k^t A V_k - I||_max over the recorded iterations, using a
+    fresh product A V_k (not the stored A-images)."""
+    worst = 0.0
+    for V, _ in res.extra["V"]:
+        G = V.T @ (A @ V)
+        worst = max(worst, float(np.abs(G - np.eye(G.shape[0])).max()))
+    return worst
+
+
+def cross_block_violation(res, A) -> float:
+    """max_k ||V_k^t A V_{k-1}||_max: consecutive s-step bases are
+    A-orthogonal (SRE-CG keeps the last 2t vectors, which in exact
+    arithmetic suffices for A-orthogonality to all earlier blocks)."""
+    worst = 0.0
+    Vs = res.extra["V"]
+    for k in range(1, len(Vs)):
+        worst = max(worst, float(np.abs(Vs[k][0].T @ (A @ Vs[k - 1][0])).max()))
+    return worst
+
+
+def petrov_galerkin_violation(res) -> float:
+    """max_k ||V_k^t r_k|| / ||r_{k-1}|| with r the method's residual:
+    r_k is orthogonal to the enlarged Krylov subspace (eqs (1)-(3))."""
+    worst = 0.0
+    rs = res.extra["rs"]
+    for k, (V, _) in enumerate(res.extra["V"]):
+        worst = max(worst, float(np.linalg.norm(V.T @ rs[k + 1]) / np.linalg.norm(rs[k])))
+    return worst
+
+
+def error_drop_violation(res, A, xstar, floor=1e-4) -> float:
+    """With V^t A V = I and alpha = V^t r_{k-1} (eqs (1)-(3)),
+    ||e_k||_A^2 = ||e_{k-1}||_A^2 - ||alpha_k||^2 for e = x* - x.  Returns
+    the largest relative violation over iterations whose starting residual
+    is above `floor` times the initial one (below that, cancellation in the
+    energy difference dominates)."""
+    worst = 0.0
+    xs, rs = res.extra["xs"], res.extra["rs"]
+    for k, a in enumerate(res.extra["alpha"]):
+        if np.linalg.norm(rs[k]) < floor * np.linalg.norm(rs[0]):
+            break
+        e0 = xstar - xs[k]
+        e1 = xstar - xs[k + 1]
+        E0 = float(e0 @ (A @ e0))
+        E1 = float(e1 @ (A @ e1))
+        worst = max(worst, abs(E1 - (E0 - float(a @ a))) / E0)
+    return worst
+
+
+def monotone_energy_violation(res, A, xstar) -> float:
+    """Largest increase of ||x* - x_k||_A relative to its predecessor."""
+    worst = 0.0
+    prev = None
+    for x in res.extra["xs"]:
+        e = xstar - x
+        E = math.sqrt(float(e @ (A @ e)))
+        if prev is not None:
+            worst = max(worst, (E - prev) / prev)
+        prev = E
+    return worst
