@@ -1,0 +1,224 @@
+/*
+ * ecg.h -- C ABI of the s-step enlarged Conjugate Gradient solver for one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Moufawad, "Numerical Stability of s-step Enlarged Krylov Subspace
+ * Conjugate Gradient methods" (arXiv 1804.10629).  The problem is A x = b
+ * with A (n x n) symmetric positive definite (Section 3.1, the input lines
+ * of the s-step algorithms).  The residual is split over t domains of the
+ * graph of A by the operator T (Section 2); every s-step iteration builds
+ * s*t A-orthonormal basis vectors V of the enlarged Krylov subspace and
+ * updates alpha = V^t r, x += V alpha, r -= A V alpha (eqs (1)-(3) and the
+ * algorithms "s-step SRE-CG" and "s-step SRE-CG2" of Section 3.1).
+ *
+ * Conventions
+ *   - Every function returning int returns an ecg status: 0 (ECG_OK),
+ *     a positive solver outcome, or a negative error.  No C++ exception
+ *     crosses this interface.
+ *   - Matrices are CSR with 0-based int32 indices, rows of the caller's
+ *     ordering; dense n x k blocks are row-major (k values per row,
+ *     contiguous).
+ *   - Array arguments are host pointers, unless the context was created
+ *     with opts.device_ptrs = 1, in which case every array argument of
+ *     calls on that context (setup included) is a device pointer on the
+ *     current HIP device.  The caller keeps ownership of all its arrays;
+ *     the library copies what it keeps.
+ *   - All work is enqueued on opts.hip_stream (0 = the null stream) and the
+ *     calls return after it has completed.  A context is not re-entrant:
+ *     calls on one context must not overlap.  Distinct contexts are
+ *     independent.
+ */
+#ifndef ECG_H
+#define ECG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define ECG_OK          0  /* converged: true residual <= tol * ||b - A x0|| */
+#define ECG_MAXIT       1  /* iteration budget spent; x is the last iterate */
+#define ECG_BREAKDOWN   2  /* a Cholesky pivot of a basis Gram matrix was <= 0
+                              or not finite; x is the last completed iterate */
+#define ECG_STAGNATED   3  /* the recursive residual met tol but the true
+                              residual did not, after opts.max_restarts
+                              residual replacements */
+#define ECG_EINVAL     -1  /* invalid argument (message: ecg_last_error) */
+#define ECG_ENOMEM     -2  /* device allocation failed */
+#define ECG_EDEVICE    -3  /* HIP runtime error or no usable gfx950 device */
+#define ECG_ENOTSUP    -4  /* valid request this build does not support */
+
+/* ---- options ----------------------------------------------------------- */
+enum ecg_variant   { ECG_SRECG = 0,   /* s-step SRE-CG: each block against the
+                                         previous two (Section 3.1) */
+                     ECG_SRECG2 = 1   /* s-step SRE-CG2: against every block
+                                         since the last (re)start */ };
+enum ecg_orth      { ECG_ACHOLQR = 0, ECG_PRECHOLQR = 1 };
+enum ecg_precision { ECG_FP64 = 0,    /* everything in binary64 */
+                     ECG_MIXED = 1    /* binary32 basis blocks and matrix values
+                                         for the basis product; Gram matrices,
+                                         Cholesky factors, alpha, x and r in
+                                         binary64; residual replacement in
+                                         binary64 whenever the recursive
+                                         residual has dropped by inner_tol */ };
+
+typedef struct ecg_opts {
+  int32_t variant;        /* enum ecg_variant (default ECG_SRECG) */
+  int32_t orth;           /* enum ecg_orth (default ECG_ACHOLQR) */
+  int32_t precision;      /* enum ecg_precision (default ECG_FP64) */
+  int32_t device_ptrs;    /* 0: host arrays, 1: device arrays (default 0) */
+  double  inner_tol;      /* ECG_MIXED: restart from the true residual when the
+                             recursive residual is <= inner_tol times the one
+                             at the last restart (default 1e-5; ignored in
+                             ECG_FP64) */
+  int32_t max_restarts;   /* bound on residual replacements (default 20) */
+  int32_t q_cap_blocks;   /* ECG_SRECG2: stored blocks before a forced restart;
+                             0 = as many as ws_cap_bytes allows (default 0) */
+  int64_t ws_cap_bytes;   /* device workspace cap; 0 = 90% of free memory */
+  void*   hip_stream;     /* hipStream_t to run on; NULL = null stream */
+  int32_t collect_stats;  /* 1: time every kernel with HIP events (ecg_last_stats) */
+  int32_t grid;           /* work-groups per streaming kernel; 0 = automatic */
+  int32_t reserved[6];    /* must be zero */
+} ecg_opts;
+
+/* Fill *o with the defaults above. */
+void ecg_opts_default(ecg_opts* o);
+
+/* ---- results and statistics -------------------------------------------- */
+typedef struct ecg_result {
+  int32_t status;         /* same value as the ecg_solve return */
+  int32_t iters;          /* s-step iterations executed, restarts included */
+  int32_t hist_len;       /* entries written to reshist */
+  int32_t restarts;       /* residual replacements performed */
+  int32_t blocks;         /* t-column basis blocks built */
+  int32_t reserved;
+  double  rho0;           /* ||b - A x0||_2 */
+  double  relres;         /* last recursive residual norm / rho0 */
+  double  true_relres;    /* ||b - A x||_2 / rho0 at exit, in binary64 */
+  double  solve_ms;       /* device time of the solve (HIP events) */
+} ecg_result;
+
+/* Kernel classes timed when opts.collect_stats = 1. */
+enum ecg_kclass {
+  ECG_K_RESID = 0,   /* r = b - A x and ||r|| */
+  ECG_K_TSPLIT,      /* T(r) */
+  ECG_K_CGS_GRAM,    /* first CGS2 update fused with the second Gram */
+  ECG_K_CGS_UPDATE,  /* second CGS2 update */
+  ECG_K_SPMM,        /* A Z with the A-CholQR Gram and the next block's Grams */
+  ECG_K_XR_UPDATE,   /* x += V alpha, r -= A V alpha, ||r|| */
+  ECG_K_GRAM,        /* stand-alone Gram (SRE-CG2, Pre-CholQR) */
+  ECG_K_UPDATE,      /* stand-alone block update (SRE-CG2, Pre-CholQR) */
+  ECG_K_OTHER,
+  ECG_K_COUNT
+};
+
+typedef struct ecg_stats {
+  int64_t launches[ECG_K_COUNT];
+  double  ms[ECG_K_COUNT];       /* summed device time */
+  double  bytes[ECG_K_COUNT];    /* summed algorithmic HBM bytes */
+  double  flops[ECG_K_COUNT];    /* summed algorithmic floating-point operations */
+} ecg_stats;
+
+/* ---- library ----------------------------------------------------------- */
+const char* ecg_version(void);
+const char* ecg_strerror(int status);
+/* Message of the last error raised on the calling thread ("" if none). */
+const char* ecg_last_error(void);
+/* Name of a kernel class, or NULL. */
+const char* ecg_kclass_name(int k);
+
+typedef struct ecg_ctx ecg_ctx;
+
+/*
+ * Geometric domain decomposition of an nx x ny x nz grid (rows numbered
+ * i + nx*(j + ny*k)) into px*py*pz boxes: row -> floor(i*px/nx) +
+ * px*(floor(j*py/ny) + py*floor(k*pz/nz)).  The paper decomposes the graph
+ * of A into t domains with Metis (Section 4); this is the box
+ * decomposition used in its place for grid problems.  dom_dev: device
+ * array of nx*ny*nz int32 written by a GPU kernel on `stream`.  Errors:
+ * ECG_EINVAL (non-positive sizes, a part count larger than its axis,
+ * nx*ny*nz >= 2^31, NULL pointer), ECG_EDEVICE.
+ */
+int ecg_partition_grid(int64_t nx, int64_t ny, int64_t nz, int32_t px, int32_t py,
+                       int32_t pz, int32_t* dom_dev, void* stream);
+
+/*
+ * Create a solver for the n x n SPD matrix (rowptr, colind, vals) with the
+ * t domains partition[i] in [0, t) and s blocks per iteration.
+ * Copies everything to device memory and allocates the workspace: (s+2)
+ * pairs of n x t blocks (basis W and its A-image) for ECG_SRECG, up to
+ * q_cap_blocks pairs for ECG_SRECG2, plus scratch.
+ * Errors: ECG_EINVAL (out == NULL; n <= 0; t < 1; t > 64; t > n; s < 1;
+ * rowptr not starting at 0 or decreasing; nnz >= 2^31; a column index out
+ * of [0, n); a partition value out of [0, t); an empty domain; a
+ * non-finite value; nonzero reserved fields), ECG_ENOMEM (the workspace
+ * does not fit ws_cap_bytes or device memory), ECG_EDEVICE.  Symmetry and
+ * definiteness are not checked here; an indefinite matrix is reported by
+ * ecg_solve as ECG_BREAKDOWN.  On error *out is NULL.
+ */
+int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const int32_t* colind,
+              const double* vals, const int32_t* partition, int32_t t, int32_t s,
+              const ecg_opts* opts);
+
+/*
+ * Solve A x = b.  x holds x0 on entry and the solution on exit.  The
+ * iteration follows the s-step algorithms of Section 3.1: it stops when the
+ * recursive residual norm rho_k <= tol * rho_0 (rho_0 = ||b - A x0||), then
+ * checks the true residual b - A x and, if that is above tol * rho_0,
+ * restarts from x with r = b - A x (at most opts.max_restarts times).
+ * maxit bounds the s-step iterations executed (restarts included).
+ * reshist (may be NULL) receives rho_0, then rho_k after every iteration and
+ * the true residual norm at every restart, at most reshist_cap values;
+ * res (may be NULL) receives counts and norms.
+ * Returns ECG_OK, ECG_MAXIT, ECG_BREAKDOWN or ECG_STAGNATED, or ECG_EINVAL
+ * (NULL c/b/x; tol <= 0 or not finite; maxit < 0; reshist_cap < 0; a
+ * non-finite entry in b or x0), ECG_EDEVICE.
+ */
+int ecg_solve(ecg_ctx* c, const double* b, double* x, double tol, int32_t maxit,
+              double* reshist, int32_t reshist_cap, ecg_result* res);
+
+/*
+ * Gradient of a loss through x = A^{-1} b with respect to the stored
+ * nonzeros: grad_vals[p] = -lambda[row(p)] * x[col(p)] for every stored
+ * entry p, in the caller's CSR order, where lambda solves A lambda = dL/dx
+ * (the adjoint; A is symmetric).  Arrays: lambda and x of length n,
+ * grad_vals of length nnz.  Errors: ECG_EINVAL (NULL argument),
+ * ECG_EDEVICE.
+ */
+int ecg_sddmm(ecg_ctx* c, const double* lambda, const double* x, double* grad_vals);
+
+/*
+ * y = A X for a row-major n x k block X (1 <= k <= 64), binary64, with the
+ * solver's sparse-times-block kernel.  Errors: ECG_EINVAL, ECG_EDEVICE.
+ */
+int ecg_spmm(ecg_ctx* c, const double* X, double* Y, int32_t k);
+
+/*
+ * Z = T(r): the n x t row-major block whose column d holds r on the rows
+ * of domain d and zero elsewhere (Section 2).  Errors: ECG_EINVAL,
+ * ECG_EDEVICE.
+ */
+int ecg_tsplit(ecg_ctx* c, const double* r, double* Z);
+
+/*
+ * The basis of the last completed s-step iteration of the last solve:
+ * V = [W_j .. W_{j+s-1}] and A V, each n x (s*t) row-major, binary64
+ * (block-major, then domain order).  Errors: ECG_EINVAL (no completed
+ * iteration), ECG_EDEVICE.
+ */
+int ecg_get_basis(ecg_ctx* c, double* V, double* AV);
+
+/* Per-kernel-class statistics of the last ecg_solve (zeros unless
+ * opts.collect_stats = 1). */
+int ecg_last_stats(ecg_ctx* c, ecg_stats* st);
+
+/* Release a context and all its device memory.  NULL is a no-op. */
+void ecg_destroy(ecg_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ECG_H */

@@ -1,0 +1,125 @@
+// Internal declarations shared by the HIP kernels and the host driver.
+// Not part of the public interface (include/ecg.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ecg {
+
+// A basis block of width t is stored row-major with TPI >= t columns
+// (TPI in {16, 32, 64}); columns t..TPI-1 are kept at zero.
+constexpr int kThreads = 256;     // threads per work-group of the block kernels
+constexpr int kMaxS = 16;         // largest s supported by the x/r update
+
+// Deterministic two-level grid reduction: every work-group writes its
+// partial vector; the last work-group of each group of `group_size` sums
+// its group in index order; the last group finisher sums the group sums in
+// index order and runs the tail.  Counters are reset by the finishers, so
+// the next launch starts from zero.
+struct RedCtl {
+  double* partials;      // [grid][L]
+  double* groups;        // [ngroups][L]
+  unsigned* counters;    // [ngroups + 1]
+  int group_size;
+};
+
+// Device-side scalars the host reads back once per s-step iteration.
+struct DevStatus {
+  double rho;            // ||r|| after the last x/r update
+  double rho_true;       // ||b - A x|| from the last residual kernel
+  int breakdown;         // 1 once a Cholesky pivot failed
+  int breakdown_block;   // block index (since restart) of the failure
+};
+
+// Arguments of the small-algebra tails run by the last work-group.
+struct TailArgs {
+  int t;                       // active columns (<= TPI)
+  int m;                       // block index since the last restart (1-based)
+  double* rinv_cur;            // R^{-1} of the block just built (write), TPI x TPI
+  const double* rinv_p1;       // R^{-1} of block m-1 (nullable)
+  const double* rinv_p2;       // R^{-1} of block m-2 (nullable)
+  double* cnext;               // [3][TPI*TPI] coefficients of the next first CGS pass
+  double* dcoef;               // [2][TPI*TPI] coefficients of the second CGS pass
+  double* beta;                // [TPI] x/r coefficients of the block just built
+  DevStatus* status;
+  double* sums_out;            // copy of the reduced sums (nullable)
+  int which;                   // TAIL_NORM: 0 -> status.rho, 1 -> status.rho_true
+};
+
+enum TailKind { TAIL_NONE = 0, TAIL_SPMM = 1, TAIL_CGS = 2, TAIL_NORM = 3, TAIL_PRE = 4 };
+
+template <typename S>
+struct UGArgs {
+  const S* X[4];        // update operands; X[0] enters with the identity when ident0
+  const double* C[4];   // TPI x TPI coefficient matrices (device)
+  const S* P[3];        // left operands of the Grams H_g = P_g^t out
+  S* out;               // written when write_out
+  int64_t n;
+  RedCtl rc;
+  TailArgs tail;
+};
+
+template <typename S, typename SA>
+struct SpArgs {
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const SA* vals;
+  const S* Z;           // input block (row-major, TPI columns)
+  S* AZ;                // output block
+  const S* AZprev;      // A-image of the previous block (E Gram), nullable
+  const double* rvec;   // residual for a = Z^t r, nullable
+  int64_t n;
+  RedCtl rc;
+  TailArgs tail;
+};
+
+template <typename S>
+struct XRArgs {
+  const S* U[kMaxS];
+  const S* AU[kMaxS];
+  const double* beta[kMaxS];   // [TPI] each
+  int nb;
+  double* x;
+  double* r;
+  int64_t n;
+  const DevStatus* status_in;  // skip everything after a breakdown
+  RedCtl rc;
+  TailArgs tail;
+};
+
+// Launchers (defined in ecg_kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_partition(int64_t nx, int64_t ny, int64_t nz, int px, int py, int pz,
+                            int32_t* dom, hipStream_t st);
+
+hipError_t launch_resid(const int32_t* rowptr, const int32_t* colind, const double* vals,
+                        const double* b, const double* x, double* r, int64_t n, int grid,
+                        RedCtl rc, TailArgs tail, hipStream_t st);
+
+template <int TPI, typename S>
+hipError_t launch_tsplit(const double* r, const int32_t* dom, S* Z, int64_t n, int grid,
+                         hipStream_t st);
+
+template <int TPI, typename S>
+hipError_t launch_update_gram(int nu, int ng, bool ident0, bool write_out, int tail,
+                              const UGArgs<S>& a, int grid, hipStream_t st);
+
+template <int TPI, typename S, typename SA>
+hipError_t launch_spmm(bool grams, bool has_prev, int tail, const SpArgs<S, SA>& a, int grid,
+                       hipStream_t st);
+
+template <int TPI, typename S>
+hipError_t launch_xr(const XRArgs<S>& a, int grid, hipStream_t st);
+
+template <int TPI, typename S>
+hipError_t launch_basis_export(const S* U, const double* rinv, double* V, int64_t n, int t,
+                               int ldv, int col0, hipStream_t st);
+
+hipError_t launch_sddmm(const int32_t* rowptr, const int32_t* colind, const double* lam,
+                        const double* x, double* grad, int64_t n, hipStream_t st);
+
+hipError_t launch_pack(const double* X, int k, double* Xp, int TPI, int64_t n, hipStream_t st);
+hipError_t launch_unpack(const double* Xp, int TPI, double* X, int k, int64_t n,
+                         hipStream_t st);
+
+}  // namespace ecg

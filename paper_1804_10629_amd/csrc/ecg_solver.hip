@@ -1,0 +1,919 @@
+// Host driver and C ABI of the s-step enlarged CG solver.
+//
+// Method (Moufawad, arXiv 1804.10629, Section 3.1, algorithms "s-step
+// SRE-CG" and "s-step SRE-CG2"; update by eqs (1)-(3)):
+//   r = b - A x, rho_0 = ||r||
+//   per s-step iteration: s blocks W_j (t columns), the first after a
+//   (re)start from T(r), the others from A W_{j-1}; each A-orthonormalized
+//   against W_{j-2}, W_{j-1} by CGS2 and against itself by A-CholQR;
+//   alpha = V^t r, x += V alpha, r -= A V alpha, rho = ||r||.
+//
+// Representation used on the device: block j is stored unnormalized as
+// U_j (the CGS2 output) and its product A U_j, together with R_j^{-1} from
+// the Cholesky factor of U_j^t A U_j; W_j = U_j R_j^{-1} and
+// A W_j = (A U_j) R_j^{-1} are never formed.  Every use of W_j folds R_j^{-1}
+// into the small coefficient matrices of the block kernels, which saves one
+// full read-and-write pass over two n x t blocks per basis block.  In exact
+// arithmetic the iterates are those of the algorithm; the first CGS2 Gram
+// of block j+1, (A W_p)^t A W_j, comes from the product kernel of block j.
+
+#include "ecg_kernels.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "ecg.h"
+
+using namespace ecg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ECG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+const char* kclass_names[ECG_K_COUNT] = {"resid",  "tsplit", "cgs_gram", "cgs_update", "spmm",
+                                         "xr_update", "gram", "update", "other"};
+
+struct Timed {
+  int k;
+  hipEvent_t a, b;
+  double bytes, flops;
+};
+
+}  // namespace
+
+struct ecg_ctx {
+  int64_t n = 0, nnz = 0;
+  int t = 0, s = 0, tpi = 16;
+  ecg_opts o{};
+  hipStream_t st = nullptr;
+  int dev = 0;
+  int sbytes = 8;   // bytes per basis element
+
+  int32_t* rowptr = nullptr;
+  int32_t* colind = nullptr;
+  int32_t* dom = nullptr;
+  double* vals = nullptr;
+  float* vals32 = nullptr;
+  double* b = nullptr;
+  double* x = nullptr;
+  double* r = nullptr;
+
+  int nslot = 0;
+  std::vector<void*> U, AU;
+  void* Zp = nullptr;
+  double* rinv = nullptr;     // [nslot][T2]
+  double* beta = nullptr;     // [nslot][tpi]
+  double* cnext = nullptr;    // [3][T2]
+  double* dcoef = nullptr;    // [2][T2]
+  double* scratch = nullptr;  // op buffers (n * tpi doubles, lazily)
+  double* scratch2 = nullptr;
+  DevStatus* status = nullptr;
+  DevStatus* h_status = nullptr;   // pinned
+
+  double* partials = nullptr;
+  double* groups = nullptr;
+  unsigned* counters = nullptr;
+  int grid = 1024;
+  int group_size = 32;
+
+  // basis of the last completed iteration
+  int last_nb = 0;
+  int last_slots[kMaxS];
+
+  ecg_stats stats{};
+  std::vector<Timed> pending;
+  std::vector<hipEvent_t> free_events;
+  hipEvent_t ev_solve0 = nullptr, ev_solve1 = nullptr;
+
+  RedCtl rc() const { return RedCtl{partials, groups, counters, group_size}; }
+  int T2() const { return tpi * tpi; }
+  double blk_bytes() const { return (double)n * t * sbytes; }
+  double csr_bytes(int vb) const { return (double)nnz * (vb + 4) + 4.0 * (n + 1); }
+
+  hipEvent_t get_event() {
+    if (!free_events.empty()) {
+      hipEvent_t e = free_events.back();
+      free_events.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  // start timing a launch of class k
+  void tstart(Timed& tm, int k, double bytes, double flops) {
+    tm.k = k;
+    tm.bytes = bytes;
+    tm.flops = flops;
+    tm.a = tm.b = nullptr;
+    if (!o.collect_stats) return;
+    tm.a = get_event();
+    tm.b = get_event();
+    if (tm.a) (void)hipEventRecord(tm.a, st);
+  }
+  void tstop(Timed& tm) {
+    stats.launches[tm.k] += 1;
+    stats.bytes[tm.k] += tm.bytes;
+    stats.flops[tm.k] += tm.flops;
+    if (!o.collect_stats || !tm.a || !tm.b) return;
+    (void)hipEventRecord(tm.b, st);
+    pending.push_back(tm);
+  }
+  // after a stream synchronisation
+  void flush_timing() {
+    for (auto& tm : pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, tm.a, tm.b) == hipSuccess) stats.ms[tm.k] += ms;
+      free_events.push_back(tm.a);
+      free_events.push_back(tm.b);
+    }
+    pending.clear();
+  }
+};
+
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+void ecg_opts_default(ecg_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->variant = ECG_SRECG;
+  o->orth = ECG_ACHOLQR;
+  o->precision = ECG_FP64;
+  o->device_ptrs = 0;
+  o->inner_tol = 1e-5;
+  o->max_restarts = 20;
+  o->q_cap_blocks = 0;
+  o->ws_cap_bytes = 0;
+  o->hip_stream = nullptr;
+  o->collect_stats = 0;
+  o->grid = 0;
+}
+
+const char* ecg_version(void) { return "ecg-mi355x 0.1.0 (gfx950)"; }
+
+const char* ecg_strerror(int s) {
+  switch (s) {
+    case ECG_OK: return "converged";
+    case ECG_MAXIT: return "iteration limit reached";
+    case ECG_BREAKDOWN: return "breakdown: Gram matrix not positive definite";
+    case ECG_STAGNATED: return "true residual stagnated above tolerance";
+    case ECG_EINVAL: return "invalid argument";
+    case ECG_ENOMEM: return "out of device memory";
+    case ECG_EDEVICE: return "HIP device error";
+    case ECG_ENOTSUP: return "not supported";
+    default: return "unknown status";
+  }
+}
+
+const char* ecg_last_error(void) { return g_last_error.c_str(); }
+
+const char* ecg_kclass_name(int k) {
+  if (k < 0 || k >= ECG_K_COUNT) return nullptr;
+  return kclass_names[k];
+}
+
+}  // extern "C"
+
+namespace {
+
+int check_device() {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    int count = 0;
+    hipError_t e2 = hipGetDeviceCount(&count);
+    return fail(ECG_EDEVICE, std::string("no usable HIP device (hipGetDevice: ") +
+                                 hipGetErrorString(e) + ", hipGetDeviceCount: " +
+                                 hipGetErrorString(e2) + ", count " + std::to_string(count) + ")");
+  }
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(ECG_EDEVICE, std::string("device is ") + prop.gcnArchName + ", built for gfx950");
+  return ECG_OK;
+}
+
+// Copy `count` elements of an input array to host memory (device_ptrs mode).
+template <typename T>
+int fetch(const T* src, int64_t count, bool dev, std::vector<T>& out, const T** view) {
+  if (!dev) {
+    *view = src;
+    return ECG_OK;
+  }
+  out.resize((size_t)count);
+  HIP_TRY(hipMemcpy(out.data(), src, sizeof(T) * count, hipMemcpyDeviceToHost));
+  *view = out.data();
+  return ECG_OK;
+}
+
+template <typename T>
+int dalloc(T** p, size_t count, size_t& total) {
+  size_t bytes = std::max<size_t>(sizeof(T) * count, 256);
+  total += bytes;
+  hipError_t e = hipMalloc((void**)p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(ECG_ENOMEM, std::string("hipMalloc of ") + std::to_string(bytes) + " bytes failed");
+  }
+  return ECG_OK;
+}
+
+int pick_tpi(int t) { return t <= 16 ? 16 : (t <= 32 ? 32 : 64); }
+
+int rows_per_wg(int tpi) { return tpi == 16 ? 64 : (tpi == 32 ? 32 : 16); }
+
+}  // namespace
+
+extern "C" void ecg_destroy(ecg_ctx* c) {
+  if (!c) return;
+  auto f = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  f(c->rowptr); f(c->colind); f(c->dom); f(c->vals); f(c->vals32);
+  f(c->b); f(c->x); f(c->r);
+  for (void* p : c->U) f(p);
+  for (void* p : c->AU) f(p);
+  f(c->Zp); f(c->rinv); f(c->beta); f(c->cnext); f(c->dcoef);
+  f(c->scratch); f(c->scratch2); f(c->status);
+  f(c->partials); f(c->groups); f(c->counters);
+  if (c->h_status) (void)hipHostFree(c->h_status);
+  for (auto& tm : c->pending) {
+    (void)hipEventDestroy(tm.a);
+    (void)hipEventDestroy(tm.b);
+  }
+  for (auto e : c->free_events) (void)hipEventDestroy(e);
+  if (c->ev_solve0) (void)hipEventDestroy(c->ev_solve0);
+  if (c->ev_solve1) (void)hipEventDestroy(c->ev_solve1);
+  delete c;
+}
+
+extern "C" int ecg_partition_grid(int64_t nx, int64_t ny, int64_t nz, int32_t px, int32_t py,
+                                  int32_t pz, int32_t* dom_dev, void* stream) {
+  if (!dom_dev) return fail(ECG_EINVAL, "dom_dev is NULL");
+  if (nx <= 0 || ny <= 0 || nz <= 0 || px <= 0 || py <= 0 || pz <= 0)
+    return fail(ECG_EINVAL, "grid and part counts must be positive");
+  if (px > nx || py > ny || pz > nz) return fail(ECG_EINVAL, "more parts than cells along an axis");
+  if (nx * ny > (int64_t(1) << 31) || nx * ny * nz >= (int64_t(1) << 31))
+    return fail(ECG_EINVAL, "grid too large for int32 row indices");
+  int rc = check_device();
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(launch_partition(nx, ny, nz, px, py, pz, dom_dev, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return ECG_OK;
+}
+
+extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const int32_t* colind,
+                         const double* vals, const int32_t* partition, int32_t t, int32_t s,
+                         const ecg_opts* opts) {
+  if (!out) return fail(ECG_EINVAL, "out is NULL");
+  *out = nullptr;
+  ecg_opts o;
+  if (opts) o = *opts;
+  else ecg_opts_default(&o);
+  for (int i = 0; i < 6; ++i)
+    if (o.reserved[i] != 0) return fail(ECG_EINVAL, "reserved option fields must be zero");
+  if (!rowptr || !colind || !vals || !partition) return fail(ECG_EINVAL, "NULL array argument");
+  if (n <= 0) return fail(ECG_EINVAL, "n must be positive");
+  if (n >= (int64_t(1) << 31)) return fail(ECG_EINVAL, "n must be < 2^31");
+  if (t < 1 || t > 64) return fail(ECG_EINVAL, "t must be in [1, 64]");
+  if (t > n) return fail(ECG_EINVAL, "t must not exceed n");
+  if (s < 1 || s > kMaxS) return fail(ECG_EINVAL, "s must be in [1, 16]");
+  if (o.variant != ECG_SRECG && o.variant != ECG_SRECG2) return fail(ECG_EINVAL, "bad variant");
+  if (o.orth != ECG_ACHOLQR && o.orth != ECG_PRECHOLQR) return fail(ECG_EINVAL, "bad orth");
+  if (o.precision != ECG_FP64 && o.precision != ECG_MIXED) return fail(ECG_EINVAL, "bad precision");
+  if (o.device_ptrs != 0 && o.device_ptrs != 1) return fail(ECG_EINVAL, "bad device_ptrs");
+  if (!(o.inner_tol >= 0.0 && o.inner_tol < 1.0)) return fail(ECG_EINVAL, "inner_tol must be in [0, 1)");
+  if (o.max_restarts < 0 || o.q_cap_blocks < 0 || o.ws_cap_bytes < 0 || o.grid < 0)
+    return fail(ECG_EINVAL, "negative option");
+  if (o.variant == ECG_SRECG2) return fail(ECG_ENOTSUP, "SRE-CG2 is not available in this build");
+  if (o.orth == ECG_PRECHOLQR) return fail(ECG_ENOTSUP, "Pre-CholQR is not available in this build");
+  const bool dev = o.device_ptrs == 1;
+  if (dev) {
+    int rc = check_device();
+    if (rc) return rc;
+  }
+
+  // ---- validate on the host ----
+  std::vector<int32_t> hrp, hci, hdom;
+  std::vector<double> hv;
+  const int32_t *rp = nullptr, *ci = nullptr, *pd = nullptr;
+  const double* vv = nullptr;
+  int rc = fetch(rowptr, n + 1, dev, hrp, &rp);
+  if (rc) return rc;
+  if (rp[0] != 0) return fail(ECG_EINVAL, "rowptr[0] must be 0");
+  for (int64_t i = 0; i < n; ++i)
+    if (rp[i + 1] < rp[i]) return fail(ECG_EINVAL, "rowptr must be non-decreasing");
+  const int64_t nnz = rp[n];
+  if (nnz <= 0) return fail(ECG_EINVAL, "matrix has no nonzeros");
+  rc = fetch(colind, nnz, dev, hci, &ci);
+  if (rc) return rc;
+  for (int64_t p = 0; p < nnz; ++p)
+    if (ci[p] < 0 || ci[p] >= n) return fail(ECG_EINVAL, "column index out of range");
+  rc = fetch(vals, nnz, dev, hv, &vv);
+  if (rc) return rc;
+  for (int64_t p = 0; p < nnz; ++p)
+    if (!std::isfinite(vv[p])) return fail(ECG_EINVAL, "non-finite matrix value");
+  rc = fetch(partition, n, dev, hdom, &pd);
+  if (rc) return rc;
+  std::vector<int64_t> dsize(t, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (pd[i] < 0 || pd[i] >= t) return fail(ECG_EINVAL, "partition value out of [0, t)");
+    dsize[pd[i]]++;
+  }
+  for (int d = 0; d < t; ++d)
+    if (dsize[d] == 0) return fail(ECG_EINVAL, "empty domain " + std::to_string(d));
+
+  rc = check_device();
+  if (rc) return rc;
+
+  ecg_ctx* c = new ecg_ctx();
+  c->n = n;
+  c->nnz = nnz;
+  c->t = t;
+  c->s = s;
+  c->tpi = pick_tpi(t);
+  c->o = o;
+  c->st = (hipStream_t)o.hip_stream;
+  c->sbytes = o.precision == ECG_MIXED ? 4 : 8;
+  (void)hipGetDevice(&c->dev);
+  const int tpi = c->tpi, T2 = tpi * tpi;
+  const size_t blk = (size_t)n * tpi;
+
+  // grid of the streaming kernels
+  {
+    int64_t steps = (n + rows_per_wg(tpi) - 1) / rows_per_wg(tpi);
+    int g = o.grid > 0 ? o.grid : (int)std::min<int64_t>(steps, tpi == 64 ? 512 : 1024);
+    c->grid = std::max(1, g);
+  }
+  const int max_grid = std::max(c->grid, 1024);
+  const int ngroups = (max_grid + c->group_size - 1) / c->group_size;
+  const size_t L = 3 * (size_t)T2 + tpi;
+
+  // ---- workspace size check ----
+  c->nslot = s + 2;
+  const size_t esz = c->sbytes;
+  double need = 2.0 * c->nslot * blk * esz + blk * esz + (double)nnz * (4 + 8 + (o.precision ? 4 : 0)) +
+                4.0 * (n + 1) + 4.0 * n + 3.0 * 8 * n + (double)max_grid * L * 8 +
+                (double)ngroups * L * 8;
+  size_t freeb = 0, totalb = 0;
+  HIP_TRY(hipMemGetInfo(&freeb, &totalb));
+  double cap = o.ws_cap_bytes > 0 ? (double)o.ws_cap_bytes : 0.9 * (double)freeb;
+  if (need > cap) {
+    delete c;
+    return fail(ECG_ENOMEM, "workspace of " + std::to_string(need) + " bytes exceeds the cap of " +
+                                std::to_string(cap));
+  }
+
+  size_t total = 0;
+  auto cleanup = [&](int code) {
+    ecg_destroy(c);
+    return code;
+  };
+#define ALLOC(ptr, type, count)                       \
+  do {                                                \
+    int r_ = dalloc<type>(&(ptr), (count), total);    \
+    if (r_) return cleanup(r_);                       \
+  } while (0)
+  ALLOC(c->rowptr, int32_t, n + 1);
+  ALLOC(c->colind, int32_t, nnz);
+  ALLOC(c->vals, double, nnz);
+  ALLOC(c->dom, int32_t, n);
+  ALLOC(c->b, double, n);
+  ALLOC(c->x, double, n);
+  ALLOC(c->r, double, n);
+  if (o.precision == ECG_MIXED) ALLOC(c->vals32, float, nnz);
+  c->U.assign(c->nslot, nullptr);
+  c->AU.assign(c->nslot, nullptr);
+  for (int i = 0; i < c->nslot; ++i) {
+    if (o.precision == ECG_MIXED) {
+      ALLOC(*(float**)&c->U[i], float, blk);
+      ALLOC(*(float**)&c->AU[i], float, blk);
+    } else {
+      ALLOC(*(double**)&c->U[i], double, blk);
+      ALLOC(*(double**)&c->AU[i], double, blk);
+    }
+  }
+  if (o.precision == ECG_MIXED) ALLOC(*(float**)&c->Zp, float, blk);
+  else ALLOC(*(double**)&c->Zp, double, blk);
+  ALLOC(c->rinv, double, (size_t)c->nslot * T2);
+  ALLOC(c->beta, double, (size_t)c->nslot * tpi);
+  ALLOC(c->cnext, double, 3 * (size_t)T2);
+  ALLOC(c->dcoef, double, 2 * (size_t)T2);
+  ALLOC(c->status, DevStatus, 1);
+  ALLOC(c->partials, double, (size_t)max_grid * L);
+  ALLOC(c->groups, double, (size_t)ngroups * L);
+  ALLOC(c->counters, unsigned, (size_t)ngroups + 1);
+#undef ALLOC
+  if (hipHostMalloc((void**)&c->h_status, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(ECG_ENOMEM, "pinned host allocation failed"));
+
+  const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  auto up = [&](void* dst, const void* src, size_t bytes) -> int {
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, kind, c->st));
+    return ECG_OK;
+  };
+  if ((rc = up(c->rowptr, rowptr, sizeof(int32_t) * (n + 1)))) return cleanup(rc);
+  if ((rc = up(c->colind, colind, sizeof(int32_t) * nnz))) return cleanup(rc);
+  if ((rc = up(c->vals, vals, sizeof(double) * nnz))) return cleanup(rc);
+  if ((rc = up(c->dom, partition, sizeof(int32_t) * n))) return cleanup(rc);
+  if (o.precision == ECG_MIXED) {
+    std::vector<float> v32((size_t)nnz);
+    for (int64_t p = 0; p < nnz; ++p) v32[p] = (float)vv[p];
+    if (hipMemcpy(c->vals32, v32.data(), sizeof(float) * nnz, hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(ECG_EDEVICE, "upload of binary32 values failed"));
+  }
+  // zero everything the kernels read before writing (padding columns stay zero)
+  for (int i = 0; i < c->nslot; ++i) {
+    if (hipMemsetAsync(c->U[i], 0, blk * esz, c->st) != hipSuccess ||
+        hipMemsetAsync(c->AU[i], 0, blk * esz, c->st) != hipSuccess)
+      return cleanup(fail(ECG_EDEVICE, "workspace clear failed"));
+  }
+  if (hipMemsetAsync(c->Zp, 0, blk * esz, c->st) != hipSuccess ||
+      hipMemsetAsync(c->rinv, 0, sizeof(double) * c->nslot * T2, c->st) != hipSuccess ||
+      hipMemsetAsync(c->beta, 0, sizeof(double) * c->nslot * tpi, c->st) != hipSuccess ||
+      hipMemsetAsync(c->cnext, 0, sizeof(double) * 3 * T2, c->st) != hipSuccess ||
+      hipMemsetAsync(c->dcoef, 0, sizeof(double) * 2 * T2, c->st) != hipSuccess ||
+      hipMemsetAsync(c->status, 0, sizeof(DevStatus), c->st) != hipSuccess ||
+      hipMemsetAsync(c->counters, 0, sizeof(unsigned) * (ngroups + 1), c->st) != hipSuccess)
+    return cleanup(fail(ECG_EDEVICE, "workspace clear failed"));
+  if (hipEventCreate(&c->ev_solve0) != hipSuccess || hipEventCreate(&c->ev_solve1) != hipSuccess)
+    return cleanup(fail(ECG_EDEVICE, "event creation failed"));
+  if (hipStreamSynchronize(c->st) != hipSuccess)
+    return cleanup(fail(ECG_EDEVICE, "setup synchronisation failed"));
+  *out = c;
+  return ECG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The solve
+// ---------------------------------------------------------------------------
+
+namespace {
+
+template <int TPI, typename S, typename SA>
+struct Engine {
+  ecg_ctx* c;
+  const SA* avals() const {
+    if constexpr (std::is_same<SA, float>::value) return c->vals32;
+    else return c->vals;
+  }
+  S* U(int slot) const { return (S*)c->U[slot]; }
+  S* AU(int slot) const { return (S*)c->AU[slot]; }
+  double* rinv(int slot) const { return c->rinv + (size_t)slot * TPI * TPI; }
+  double* beta(int slot) const { return c->beta + (size_t)slot * TPI; }
+
+  TailArgs tail0(int m) const {
+    TailArgs ta{};
+    ta.t = c->t;
+    ta.m = m;
+    ta.cnext = c->cnext;
+    ta.dcoef = c->dcoef;
+    ta.status = c->status;
+    return ta;
+  }
+
+  int resid(int which) {
+    TailArgs ta = tail0(0);
+    ta.which = which;
+    Timed tm;
+    c->tstart(tm, ECG_K_RESID, c->csr_bytes(8) + 24.0 * c->n, 2.0 * c->nnz + 3.0 * c->n);
+    const int g = (int)std::min<int64_t>((c->n + kThreads - 1) / kThreads, 1024);
+    HIP_TRY(launch_resid(c->rowptr, c->colind, c->vals, c->b, c->x, c->r, c->n, g, c->rc(), ta,
+                         c->st));
+    c->tstop(tm);
+    return ECG_OK;
+  }
+
+  // Build block m (1-based since the last restart) into `slot`; p1, p2 are
+  // the slots of blocks m-1 and m-2.
+  int block(int m, int slot, int p1, int p2) {
+    const double bb = c->blk_bytes();
+    const double nt2 = (double)c->n * c->t * c->t;
+    if (m == 1) {
+      Timed tm;
+      c->tstart(tm, ECG_K_TSPLIT, bb + 12.0 * c->n, 0.0);
+      HIP_TRY((launch_tsplit<TPI, S>(c->r, c->dom, U(slot), c->n, c->grid, c->st)));
+      c->tstop(tm);
+    } else {
+      const int np = m >= 3 ? 2 : 1;
+      UGArgs<S> ka{};
+      ka.X[0] = AU(p1);
+      ka.X[1] = U(p1);
+      ka.X[2] = np == 2 ? U(p2) : nullptr;
+      ka.C[0] = c->cnext;
+      ka.C[1] = c->cnext + TPI * TPI;
+      ka.C[2] = c->cnext + 2 * TPI * TPI;
+      ka.P[0] = AU(p1);
+      ka.P[1] = np == 2 ? AU(p2) : nullptr;
+      ka.out = (S*)c->Zp;
+      ka.n = c->n;
+      ka.rc = c->rc();
+      ka.tail = tail0(m);
+      ka.tail.rinv_p1 = rinv(p1);
+      ka.tail.rinv_p2 = np == 2 ? rinv(p2) : nullptr;
+      Timed tm;
+      c->tstart(tm, ECG_K_CGS_GRAM, (2.0 * np + 1.0) * bb, 2.0 * nt2 * (2 * np + 1 + np));
+      HIP_TRY((launch_update_gram<TPI, S>(np + 1, np, false, true, TAIL_CGS, ka, c->grid, c->st)));
+      c->tstop(tm);
+
+      UGArgs<S> kb{};
+      kb.X[0] = (const S*)c->Zp;
+      kb.X[1] = U(p1);
+      kb.X[2] = np == 2 ? U(p2) : nullptr;
+      kb.C[1] = c->dcoef;
+      kb.C[2] = c->dcoef + TPI * TPI;
+      kb.out = U(slot);
+      kb.n = c->n;
+      kb.rc = c->rc();
+      kb.tail = tail0(m);
+      Timed tm2;
+      c->tstart(tm2, ECG_K_CGS_UPDATE, (np + 2.0) * bb, 2.0 * nt2 * np);
+      HIP_TRY((launch_update_gram<TPI, S>(np + 1, 0, true, true, TAIL_NONE, kb, c->grid, c->st)));
+      c->tstop(tm2);
+    }
+    SpArgs<S, SA> sa{};
+    sa.rowptr = c->rowptr;
+    sa.colind = c->colind;
+    sa.vals = avals();
+    sa.Z = U(slot);
+    sa.AZ = AU(slot);
+    sa.AZprev = m >= 2 ? AU(p1) : nullptr;
+    sa.rvec = c->r;
+    sa.n = c->n;
+    sa.rc = c->rc();
+    sa.tail = tail0(m);
+    sa.tail.rinv_cur = rinv(slot);
+    sa.tail.rinv_p1 = m >= 2 ? rinv(p1) : nullptr;
+    sa.tail.beta = beta(slot);
+    Timed tm;
+    const int vb = std::is_same<SA, float>::value ? 4 : 8;
+    c->tstart(tm, ECG_K_SPMM, c->csr_bytes(vb) + (m >= 2 ? 3.0 : 2.0) * bb + 8.0 * c->n,
+              2.0 * c->nnz * c->t + 2.0 * nt2 * (m >= 2 ? 3 : 2) + 2.0 * c->n * c->t);
+    HIP_TRY((launch_spmm<TPI, S, SA>(true, m >= 2, TAIL_SPMM, sa, c->grid, c->st)));
+    c->tstop(tm);
+    return ECG_OK;
+  }
+
+  int xr(const int* slots, int nb) {
+    XRArgs<S> xa{};
+    for (int i = 0; i < nb; ++i) {
+      xa.U[i] = U(slots[i]);
+      xa.AU[i] = AU(slots[i]);
+      xa.beta[i] = beta(slots[i]);
+    }
+    xa.nb = nb;
+    xa.x = c->x;
+    xa.r = c->r;
+    xa.n = c->n;
+    xa.status_in = c->status;
+    xa.rc = c->rc();
+    xa.tail = tail0(0);
+    Timed tm;
+    c->tstart(tm, ECG_K_XR_UPDATE, 2.0 * nb * c->blk_bytes() + 32.0 * c->n,
+              4.0 * nb * (double)c->n * c->t + 2.0 * c->n);
+    const int g = (int)std::min<int64_t>((c->n + 63) / 64, 1024);
+    HIP_TRY((launch_xr<TPI, S>(xa, g, c->st)));
+    c->tstop(tm);
+    return ECG_OK;
+  }
+
+  int read_status(DevStatus* h) {
+    HIP_TRY(hipMemcpyAsync(c->h_status, c->status, sizeof(DevStatus), hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    *h = *c->h_status;
+    c->flush_timing();
+    return ECG_OK;
+  }
+
+  int run(double tol, int maxit, double* hist, int cap, ecg_result* res) {
+    int rc;
+    int hl = 0;
+    auto push = [&](double v) {
+      if (hist && hl < cap) hist[hl] = v;
+      ++hl;
+    };
+    DevStatus h{};
+    HIP_TRY(hipMemsetAsync(c->status, 0, sizeof(DevStatus), c->st));
+    if ((rc = resid(1))) return rc;
+    if ((rc = read_status(&h))) return rc;
+    const double rho0 = h.rho_true;
+    res->rho0 = rho0;
+    if (!std::isfinite(rho0)) return fail(ECG_EINVAL, "b or x0 contains a non-finite value");
+    push(rho0);
+    if (rho0 == 0.0) {
+      res->relres = res->true_relres = 0.0;
+      res->hist_len = std::min(hl, cap);
+      return ECG_OK;
+    }
+    const double thr_final = tol * rho0;
+    const double inner = c->o.precision == ECG_MIXED ? c->o.inner_tol : 0.0;
+    double rho = rho0, rho_restart = rho0;
+    int k = 0, restarts = 0, m = 0, nblocks = 0;
+    int status = ECG_OK;
+    const int ns = c->nslot;
+    int slot_of[3] = {-1, -1, -1};   // slots of blocks m, m-1, m-2
+    bool have_basis = false;
+    while (true) {
+      const double thr = std::max(inner * rho_restart, thr_final);
+      while (rho > thr && k < maxit) {
+        int slots[kMaxS];
+        for (int i = 0; i < c->s; ++i) {
+          ++m;
+          const int slot = (nblocks) % ns;
+          slot_of[2] = slot_of[1];
+          slot_of[1] = slot_of[0];
+          slot_of[0] = slot;
+          if ((rc = block(m, slot, slot_of[1], slot_of[2]))) return rc;
+          slots[i] = slot;
+          ++nblocks;
+        }
+        if ((rc = xr(slots, c->s))) return rc;
+        if ((rc = read_status(&h))) return rc;
+        if (h.breakdown) {
+          status = ECG_BREAKDOWN;
+          break;
+        }
+        rho = h.rho;
+        ++k;
+        push(rho);
+        c->last_nb = c->s;
+        for (int i = 0; i < c->s; ++i) c->last_slots[i] = slots[i];
+        have_basis = true;
+      }
+      if (status == ECG_BREAKDOWN) break;
+      if (rho > thr) {
+        status = ECG_MAXIT;
+        break;
+      }
+      if ((rc = resid(1))) return rc;   // r <- b - A x (true residual)
+      if ((rc = read_status(&h))) return rc;
+      const double tau = h.rho_true;
+      if (tau <= thr_final) {
+        status = ECG_OK;
+        rho = tau;
+        break;
+      }
+      if (restarts >= c->o.max_restarts || k >= maxit) {
+        status = k < maxit ? ECG_STAGNATED : ECG_MAXIT;
+        rho = tau;
+        break;
+      }
+      rho = tau;
+      push(tau);
+      ++restarts;
+      rho_restart = tau;
+      m = 0;
+      slot_of[0] = slot_of[1] = slot_of[2] = -1;
+    }
+    (void)have_basis;
+    // final true residual (the residual kernel leaves r = b - A x)
+    if ((rc = resid(1))) return rc;
+    if ((rc = read_status(&h))) return rc;
+    res->iters = k;
+    res->restarts = restarts;
+    res->blocks = nblocks;
+    res->relres = rho / rho0;
+    res->true_relres = h.rho_true / rho0;
+    res->hist_len = std::min(hl, cap);
+    return status;
+  }
+};
+
+template <int TPI>
+int run_tpi(ecg_ctx* c, double tol, int maxit, double* hist, int cap, ecg_result* res) {
+  if (c->o.precision == ECG_MIXED) {
+    Engine<TPI, float, float> e{c};
+    return e.run(tol, maxit, hist, cap, res);
+  }
+  Engine<TPI, double, double> e{c};
+  return e.run(tol, maxit, hist, cap, res);
+}
+
+}  // namespace
+
+extern "C" int ecg_solve(ecg_ctx* c, const double* b, double* x, double tol, int32_t maxit,
+                         double* reshist, int32_t reshist_cap, ecg_result* res) {
+  if (!c || !b || !x) return fail(ECG_EINVAL, "NULL argument");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(ECG_EINVAL, "tol must be positive and finite");
+  if (maxit < 0) return fail(ECG_EINVAL, "maxit must be >= 0");
+  if (reshist_cap < 0) return fail(ECG_EINVAL, "reshist_cap must be >= 0");
+  ecg_result tmp{};
+  if (!res) res = &tmp;
+  std::memset(res, 0, sizeof(*res));
+  std::memset(&c->stats, 0, sizeof(c->stats));
+  c->last_nb = 0;
+  const bool dev = c->o.device_ptrs == 1;
+  const hipMemcpyKind in = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  const hipMemcpyKind outk = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  HIP_TRY(hipMemcpyAsync(c->b, b, sizeof(double) * c->n, in, c->st));
+  HIP_TRY(hipMemcpyAsync(c->x, x, sizeof(double) * c->n, in, c->st));
+  HIP_TRY(hipEventRecord(c->ev_solve0, c->st));
+  int st;
+  switch (c->tpi) {
+    case 16: st = run_tpi<16>(c, tol, maxit, reshist, reshist_cap, res); break;
+    case 32: st = run_tpi<32>(c, tol, maxit, reshist, reshist_cap, res); break;
+    default: st = run_tpi<64>(c, tol, maxit, reshist, reshist_cap, res); break;
+  }
+  if (st < 0) return st;
+  HIP_TRY(hipEventRecord(c->ev_solve1, c->st));
+  HIP_TRY(hipMemcpyAsync(x, c->x, sizeof(double) * c->n, outk, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, c->ev_solve0, c->ev_solve1));
+  res->solve_ms = ms;
+  res->status = st;
+  return st;
+}
+
+extern "C" int ecg_sddmm(ecg_ctx* c, const double* lambda, const double* x, double* grad_vals) {
+  if (!c || !lambda || !x || !grad_vals) return fail(ECG_EINVAL, "NULL argument");
+  const bool dev = c->o.device_ptrs == 1;
+  const double *dl = lambda, *dx = x;
+  double* dg = grad_vals;
+  double *tl = nullptr, *tx = nullptr, *tg = nullptr;
+  if (!dev) {
+    size_t tot = 0;
+    if (dalloc(&tl, c->n, tot) || dalloc(&tx, c->n, tot) || dalloc(&tg, c->nnz, tot)) {
+      if (tl) (void)hipFree(tl);
+      if (tx) (void)hipFree(tx);
+      if (tg) (void)hipFree(tg);
+      return ECG_ENOMEM;
+    }
+    (void)hipMemcpyAsync(tl, lambda, sizeof(double) * c->n, hipMemcpyHostToDevice, c->st);
+    (void)hipMemcpyAsync(tx, x, sizeof(double) * c->n, hipMemcpyHostToDevice, c->st);
+    dl = tl;
+    dx = tx;
+    dg = tg;
+  }
+  hipError_t e = launch_sddmm(c->rowptr, c->colind, dl, dx, dg, c->n, c->st);
+  if (e == hipSuccess && !dev)
+    e = hipMemcpyAsync(grad_vals, tg, sizeof(double) * c->nnz, hipMemcpyDeviceToHost, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (tl) (void)hipFree(tl);
+  if (tx) (void)hipFree(tx);
+  if (tg) (void)hipFree(tg);
+  if (e != hipSuccess) return fail(ECG_EDEVICE, std::string("sddmm: ") + hipGetErrorString(e));
+  return ECG_OK;
+}
+
+namespace {
+int ensure_scratch(ecg_ctx* c) {
+  size_t tot = 0;
+  if (!c->scratch) {
+    int rc = dalloc(&c->scratch, (size_t)c->n * 64, tot);
+    if (rc) return rc;
+  }
+  if (!c->scratch2) {
+    int rc = dalloc(&c->scratch2, (size_t)c->n * 64, tot);
+    if (rc) return rc;
+  }
+  return ECG_OK;
+}
+
+template <int TPI>
+int spmm_op(ecg_ctx* c, double* Xp, double* Yp) {
+  SpArgs<double, double> sa{};
+  sa.rowptr = c->rowptr;
+  sa.colind = c->colind;
+  sa.vals = c->vals;
+  sa.Z = Xp;
+  sa.AZ = Yp;
+  sa.n = c->n;
+  sa.rc = c->rc();
+  const int g = (int)std::min<int64_t>((c->n + rows_per_wg(TPI) - 1) / rows_per_wg(TPI), 1024);
+  HIP_TRY((launch_spmm<TPI, double, double>(false, false, TAIL_NONE, sa, g, c->st)));
+  return ECG_OK;
+}
+}  // namespace
+
+extern "C" int ecg_spmm(ecg_ctx* c, const double* X, double* Y, int32_t k) {
+  if (!c || !X || !Y) return fail(ECG_EINVAL, "NULL argument");
+  if (k < 1 || k > 64) return fail(ECG_EINVAL, "k must be in [1, 64]");
+  int rc = ensure_scratch(c);
+  if (rc) return rc;
+  const bool dev = c->o.device_ptrs == 1;
+  const int tpi = pick_tpi(k);
+  double* Xin = c->scratch2;   // row-major n x k staging for host inputs
+  if (dev) Xin = (double*)X;
+  else HIP_TRY(hipMemcpyAsync(Xin, X, sizeof(double) * c->n * k, hipMemcpyHostToDevice, c->st));
+  // pack to n x tpi in scratch, product into scratch2 (after the pack consumed it)
+  HIP_TRY(launch_pack(Xin, k, c->scratch, tpi, c->n, c->st));
+  switch (tpi) {
+    case 16: rc = spmm_op<16>(c, c->scratch, c->scratch2); break;
+    case 32: rc = spmm_op<32>(c, c->scratch, c->scratch2); break;
+    default: rc = spmm_op<64>(c, c->scratch, c->scratch2); break;
+  }
+  if (rc) return rc;
+  if (dev) {
+    HIP_TRY(launch_unpack(c->scratch2, tpi, Y, k, c->n, c->st));
+  } else {
+    HIP_TRY(launch_unpack(c->scratch2, tpi, c->scratch, k, c->n, c->st));
+    HIP_TRY(hipMemcpyAsync(Y, c->scratch, sizeof(double) * c->n * k, hipMemcpyDeviceToHost, c->st));
+  }
+  HIP_TRY(hipStreamSynchronize(c->st));
+  return ECG_OK;
+}
+
+extern "C" int ecg_tsplit(ecg_ctx* c, const double* r, double* Z) {
+  if (!c || !r || !Z) return fail(ECG_EINVAL, "NULL argument");
+  int rc = ensure_scratch(c);
+  if (rc) return rc;
+  const bool dev = c->o.device_ptrs == 1;
+  double* rin = c->scratch2;
+  if (dev) rin = (double*)r;
+  else HIP_TRY(hipMemcpyAsync(rin, r, sizeof(double) * c->n, hipMemcpyHostToDevice, c->st));
+  double* out = c->scratch;
+  switch (c->tpi) {
+    case 16: HIP_TRY((launch_tsplit<16, double>(rin, c->dom, out, c->n, 0, c->st))); break;
+    case 32: HIP_TRY((launch_tsplit<32, double>(rin, c->dom, out, c->n, 0, c->st))); break;
+    default: HIP_TRY((launch_tsplit<64, double>(rin, c->dom, out, c->n, 0, c->st))); break;
+  }
+  double* dst = dev ? Z : c->scratch2;
+  HIP_TRY(launch_unpack(out, c->tpi, dst, c->t, c->n, c->st));
+  if (!dev)
+    HIP_TRY(hipMemcpyAsync(Z, dst, sizeof(double) * c->n * c->t, hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  return ECG_OK;
+}
+
+extern "C" int ecg_get_basis(ecg_ctx* c, double* V, double* AV) {
+  if (!c || !V || !AV) return fail(ECG_EINVAL, "NULL argument");
+  if (c->last_nb <= 0) return fail(ECG_EINVAL, "no completed iteration");
+  const bool dev = c->o.device_ptrs == 1;
+  const int st = c->last_nb * c->t;
+  size_t tot = 0;
+  double* dv = nullptr;
+  double* dav = nullptr;
+  if (!dev) {
+    if (dalloc(&dv, (size_t)c->n * st, tot) || dalloc(&dav, (size_t)c->n * st, tot)) {
+      if (dv) (void)hipFree(dv);
+      return ECG_ENOMEM;
+    }
+  } else {
+    dv = V;
+    dav = AV;
+  }
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < c->last_nb && e == hipSuccess; ++i) {
+    const int slot = c->last_slots[i];
+    const double* ri = c->rinv + (size_t)slot * c->T2();
+    const bool mixed = c->o.precision == ECG_MIXED;
+#define EXP(TPI)                                                                                \
+  if (mixed) {                                                                                  \
+    e = launch_basis_export<TPI, float>((const float*)c->U[slot], ri, dv, c->n, c->t, st,       \
+                                        i * c->t, c->st);                                       \
+    if (e == hipSuccess)                                                                        \
+      e = launch_basis_export<TPI, float>((const float*)c->AU[slot], ri, dav, c->n, c->t, st,   \
+                                          i * c->t, c->st);                                     \
+  } else {                                                                                      \
+    e = launch_basis_export<TPI, double>((const double*)c->U[slot], ri, dv, c->n, c->t, st,     \
+                                         i * c->t, c->st);                                      \
+    if (e == hipSuccess)                                                                        \
+      e = launch_basis_export<TPI, double>((const double*)c->AU[slot], ri, dav, c->n, c->t, st, \
+                                           i * c->t, c->st);                                    \
+  }
+    if (c->tpi == 16) { EXP(16) }
+    else if (c->tpi == 32) { EXP(32) }
+    else { EXP(64) }
+#undef EXP
+  }
+  if (e == hipSuccess && !dev) {
+    e = hipMemcpyAsync(V, dv, sizeof(double) * c->n * st, hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(AV, dav, sizeof(double) * c->n * st, hipMemcpyDeviceToHost, c->st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (!dev) {
+    (void)hipFree(dv);
+    (void)hipFree(dav);
+  }
+  if (e != hipSuccess) return fail(ECG_EDEVICE, std::string("get_basis: ") + hipGetErrorString(e));
+  return ECG_OK;
+}
+
+extern "C" int ecg_last_stats(ecg_ctx* c, ecg_stats* st) {
+  if (!c || !st) return fail(ECG_EINVAL, "NULL argument");
+  *st = c->stats;
+  return ECG_OK;
+}

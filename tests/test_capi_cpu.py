@@ -1,0 +1,139 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/ecg.h declares, and rejects invalid arguments before touching a
+device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1804_10629_amd as E
+import problems as P
+from tests.conftest import ROOT, gpu_available
+
+HEADER = os.path.join(ROOT, "include", "ecg.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ecg_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(E.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding declares a signature for each of them
+    assert set(names) <= set(E._SIGS)
+
+
+def test_version_and_strings():
+    assert "gfx950" in E.version()
+    for code in (0, 1, 2, 3, -1, -2, -3, -4):
+        assert E.strerror(code) and E.strerror(code) != "unknown status"
+    assert E.strerror(99) == "unknown status"
+    assert [E.lib.ecg_kclass_name(i).decode() for i in range(9)] == E.KCLASSES
+    assert E.lib.ecg_kclass_name(9) is None
+
+
+def test_opts_default():
+    o = E._Opts()
+    E.lib.ecg_opts_default(ctypes.byref(o))
+    assert (o.variant, o.orth, o.precision, o.device_ptrs) == (0, 0, 0, 0)
+    assert o.inner_tol == 1e-5 and o.max_restarts == 20 and o.grid == 0
+    assert list(o.reserved) == [0] * 6
+
+
+def _setup(n, rowptr, colind, vals, part, t, s, **kw):
+    o = E._Opts()
+    E.lib.ecg_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    ctx = ctypes.c_void_p()
+    args = [np.ascontiguousarray(a) for a in (rowptr, colind, vals, part)]
+    code = E.lib.ecg_setup(ctypes.byref(ctx), n, *(a.ctypes.data for a in args), t, s,
+                           ctypes.byref(o))
+    if ctx.value:
+        E.lib.ecg_destroy(ctx)
+    return code, E.lib.ecg_last_error().decode()
+
+
+@pytest.fixture(scope="module")
+def small():
+    p = P.poisson2d(8, t=4, parts=(2, 2, 1))
+    dom = np.repeat(np.arange(4, dtype=np.int32), 16)
+    return p, dom
+
+
+@pytest.mark.parametrize("case", [
+    "n0", "t0", "t65", "t_gt_n", "s0", "s17", "rowptr0", "decreasing", "col_range",
+    "part_range", "empty_domain", "nan_value", "reserved", "variant", "inner_tol"])
+def test_setup_rejects(small, case):
+    p, dom = small
+    rp, ci, va, pd = p.rowptr.copy(), p.colind.copy(), p.vals.copy(), dom.copy()
+    n, t, s, kw = p.n, 4, 2, {}
+    if case == "n0":
+        n = 0
+    elif case == "t0":
+        t = 0
+    elif case == "t65":
+        t = 65
+    elif case == "t_gt_n":
+        n, t = 3, 4
+        rp = rp[:4]
+    elif case == "s0":
+        s = 0
+    elif case == "s17":
+        s = 17
+    elif case == "rowptr0":
+        rp = rp + 1
+    elif case == "decreasing":
+        rp[5] = rp[7]
+    elif case == "col_range":
+        ci[3] = p.n
+    elif case == "part_range":
+        pd[0] = 4
+    elif case == "empty_domain":
+        pd[pd == 2] = 1
+    elif case == "nan_value":
+        va[10] = np.nan
+    elif case == "reserved":
+        kw = {"reserved": (ctypes.c_int32 * 6)(0, 0, 1, 0, 0, 0)}
+    elif case == "variant":
+        kw = {"variant": 7}
+    elif case == "inner_tol":
+        kw = {"inner_tol": 1.5}
+    code, msg = _setup(n, rp, ci, va, pd, t, s, **kw)
+    assert code == E.EINVAL, (case, code, msg)
+    assert msg
+
+
+def test_setup_without_gpu_reports_device_error(small):
+    if gpu_available():
+        pytest.skip("a GPU is present")
+    p, dom = small
+    code, msg = _setup(p.n, p.rowptr, p.colind, p.vals, dom, 4, 2)
+    assert code == E.EDEVICE and msg
+
+
+def test_null_arguments():
+    assert E.lib.ecg_setup(None, 1, None, None, None, None, 1, 1, None) == E.EINVAL
+    assert E.lib.ecg_solve(None, None, None, 1e-8, 10, None, 0, None) == E.EINVAL
+    assert E.lib.ecg_sddmm(None, None, None, None) == E.EINVAL
+    assert E.lib.ecg_spmm(None, None, None, 4) == E.EINVAL
+    assert E.lib.ecg_tsplit(None, None, None) == E.EINVAL
+    assert E.lib.ecg_get_basis(None, None, None) == E.EINVAL
+    assert E.lib.ecg_last_stats(None, None) == E.EINVAL
+    E.lib.ecg_destroy(None)
+
+
+@pytest.mark.parametrize("args", [(0, 4, 1, 1, 1, 1), (4, 4, 1, 5, 1, 1), (4, 4, 1, 0, 1, 1),
+                                  (1 << 16, 1 << 16, 1, 1, 1, 1)])
+def test_partition_rejects(args):
+    buf = (ctypes.c_int32 * 4)()
+    assert E.lib.ecg_partition_grid(*args, ctypes.addressof(buf), None) == E.EINVAL
+    assert E.lib.ecg_partition_grid(4, 4, 1, 1, 1, 1, None, None) == E.EINVAL

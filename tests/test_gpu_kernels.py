@@ -1,0 +1,68 @@
+"""GPU kernel parity through the C ABI: partition, T(r), sparse-times-block
+product and SDDMM against the oracle / CPU definitions."""
+import numpy as np
+import pytest
+
+import oracle as O
+import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    import paper_1804_10629_amd as E
+    return E
+
+
+@pytest.mark.parametrize("shape,parts", [
+    ((100, 100, 1), (2, 4, 1)), ((128, 128, 128), (4, 4, 1)), ((128, 128, 128), (2, 4, 4)),
+    ((1000, 1000, 1), (4, 4, 1)), ((256, 256, 256), (4, 4, 4)), ((10, 7, 3), (3, 2, 2)),
+    ((13, 1, 1), (4, 1, 1)), ((37, 29, 5), (5, 3, 2))])
+def test_partition_bit_exact(E, shape, parts):
+    dom = E.partition_grid(shape, parts).cpu().numpy()
+    want = O.partition_grid(shape, parts)
+    assert dom.dtype == np.int32
+    assert np.array_equal(dom, want)
+
+
+def _solver(E, p, t, parts, s=2, **kw):
+    dom = O.partition_grid(p.shape, parts)
+    return E.Solver(p.rowptr, p.colind, p.vals, dom, t, s, **kw), dom
+
+
+@pytest.mark.parametrize("m,t,parts", [(100, 8, (2, 4, 1)), (37, 3, (3, 1, 1)),
+                                       (40, 64, (8, 8, 1)), (33, 20, (5, 4, 1))])
+def test_tsplit_bit_exact(E, m, t, parts):
+    p = P.poisson2d(m, t=t, parts=parts)
+    sol, dom = _solver(E, p, t, parts)
+    r = np.random.default_rng(m).standard_normal(p.n)
+    Z = sol.tsplit(r).cpu().numpy()
+    assert np.array_equal(Z, O.split_T(r, dom, t))
+
+
+@pytest.mark.parametrize("k", [1, 3, 8, 16, 17, 32, 33, 64])
+def test_spmm_matches_cpu(E, k):
+    shape = (23, 19, 7)           # n = 3059: several tiles and a ragged tail
+    p = P.make_problem("rb", shape, P.kappa_random_blocks(shape, 5, block=4), seed=5, t=1,
+                       s=1, parts=(1, 1, 1))
+    sol, _ = _solver(E, p, 4, (2, 2, 1))
+    X = np.random.default_rng(k).standard_normal((p.n, k))
+    Y = sol.spmm(X).cpu().numpy()
+    A = p.scipy()
+    Yref = A @ X
+    bound = 8 * np.finfo(float).eps * (abs(A) @ np.abs(X))
+    assert (np.abs(Y - Yref) <= bound + 1e-300).all()
+
+
+def test_sddmm_bit_exact(E):
+    p = P.loguniform2d(40, t=4, parts=(2, 2, 1))
+    sol, _ = _solver(E, p, 4, (2, 2, 1))
+    rng = np.random.default_rng(1)
+    lam, x = rng.standard_normal(p.n), rng.standard_normal(p.n)
+    g = sol.sddmm(lam, x).cpu().numpy()
+    assert np.array_equal(g, O.sddmm(p.rowptr, p.colind, lam, x))
