@@ -110,7 +110,8 @@ enum ecg_kclass {
   ECG_K_XR_UPDATE,   /* x += V alpha, r -= A V alpha, ||r|| */
   ECG_K_GRAM,        /* stand-alone Gram (SRE-CG2, Pre-CholQR) */
   ECG_K_UPDATE,      /* stand-alone block update (SRE-CG2, Pre-CholQR) */
-  ECG_K_OTHER,
+  ECG_K_SMALL,       /* sums of work-group partials and the t x t algebra
+                        (Cholesky, R^{-1}, coefficient matrices) */
   ECG_K_COUNT
 };
 

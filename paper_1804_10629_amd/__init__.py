@@ -24,7 +24,9 @@ import numpy as np
 import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libecg.so")
+# ECG_LIBRARY selects another build of the library (e.g. one with different
+# kernel tuning knobs); the default is the in-tree libecg.so
+LIB_PATH = os.environ.get("ECG_LIBRARY") or os.path.join(_HERE, "libecg.so")
 
 OK, MAXIT, BREAKDOWN, STAGNATED = 0, 1, 2, 3
 EINVAL, ENOMEM, EDEVICE, ENOTSUP = -1, -2, -3, -4
@@ -32,7 +34,7 @@ SRECG, SRECG2 = 0, 1
 ACHOLQR, PRECHOLQR = 0, 1
 FP64, MIXED = 0, 1
 KCLASSES = ["resid", "tsplit", "cgs_gram", "cgs_update", "spmm", "xr_update", "gram",
-            "update", "other"]
+            "update", "small"]
 
 
 class EcgError(RuntimeError):

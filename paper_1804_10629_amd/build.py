@@ -35,9 +35,9 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build libecg.so)")
 
 
-def _compile(src: str, obj: str, verbose: bool) -> None:
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src),
-           "-o", obj]
+def _compile(src: str, obj: str, verbose: bool, defines=()) -> None:
+    cmd = [hipcc(), *HIPCC_FLAGS, *[f"-D{d}" for d in defines], "-I", INCLUDE, "-I", CSRC,
+           "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -49,22 +49,23 @@ def _compile(src: str, obj: str, verbose: bool) -> None:
         print(err, file=sys.stderr)
 
 
-def build(verbose: bool = True) -> str:
-    """Compile every HIP source and link libecg.so next to this file."""
-    objdir = os.path.join(HERE, "_build")
+def build(verbose: bool = True, out: str = LIB, defines=()) -> str:
+    """Compile every HIP source and link libecg.so next to this file (or at
+    `out`, with extra preprocessor `defines` such as the kernel tuning knobs)."""
+    objdir = os.path.join(HERE, "_build", os.path.basename(out).replace(".so", ""))
     os.makedirs(objdir, exist_ok=True)
     objs = [os.path.join(objdir, s.replace(".hip", ".o")) for s in SOURCES]
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        list(ex.map(lambda so: _compile(so[0], so[1], verbose), zip(SOURCES, objs)))
-    tmp = LIB + ".tmp"
+        list(ex.map(lambda so: _compile(so[0], so[1], verbose, defines), zip(SOURCES, objs)))
+    tmp = out + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -12,15 +12,13 @@ namespace ecg {
 constexpr int kThreads = 256;     // threads per work-group of the block kernels
 constexpr int kMaxS = 16;         // largest s supported by the x/r update
 
-// Deterministic two-level grid reduction: every work-group writes its
-// partial vector; the last work-group of each group of `group_size` sums
-// its group in index order; the last group finisher sums the group sums in
-// index order and runs the tail.  Counters are reset by the finishers, so
-// the next launch starts from zero.
+// Deterministic reduction over work-groups: every work-group of a streaming
+// kernel writes its partial vector; k_reduce_groups then sums groups of
+// `group_size` partials in index order and k_final sums the group sums in
+// index order and runs the small dense algebra (the tail).
 struct RedCtl {
   double* partials;      // [grid][L]
   double* groups;        // [ngroups][L]
-  unsigned* counters;    // [ngroups + 1]
   int group_size;
 };
 
@@ -89,6 +87,11 @@ struct XRArgs {
 };
 
 // Launchers (defined in ecg_kernels.hip).  All return hipError_t of the launch.
+// Sum the partials of a kernel that ran with G work-groups (L values each)
+// and run the tail `tail` (TAIL_SPMM, TAIL_CGS with ng Grams, TAIL_NORM).
+hipError_t launch_reduce(const RedCtl& rc, int G, int L, int tpi, int tail, int ng,
+                         const TailArgs& ta, hipStream_t st);
+
 hipError_t launch_partition(int64_t nx, int64_t ny, int64_t nz, int px, int py, int pz,
                             int32_t* dom, hipStream_t st);
 

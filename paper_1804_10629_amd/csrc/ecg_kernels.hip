@@ -62,10 +62,32 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
 template <typename S>
 __device__ __forceinline__ double ld(const S* p) { return static_cast<double>(*p); }
 
+// Tuning knobs (compile-time): row quads per lane of the block-update
+// kernels at TPI = 16 / 32, prefetch of the next step's operands, row quads
+// per lane and gather chunk of the product kernel.
+#ifndef ECG_UG_RPL16
+#define ECG_UG_RPL16 4
+#endif
+#ifndef ECG_UG_RPL32
+#define ECG_UG_RPL32 2
+#endif
+#ifndef ECG_UG_PREFETCH
+#define ECG_UG_PREFETCH 0
+#endif
+#ifndef ECG_SP_RPL16
+#define ECG_SP_RPL16 2
+#endif
+#ifndef ECG_SP_CHUNK
+#define ECG_SP_CHUNK 8
+#endif
+#ifndef ECG_SP_LDS
+#define ECG_SP_LDS 0
+#endif
+
 template <int TPI>
 struct Cfg {
   static constexpr int EPL = TPI / 16;                              // columns per lane
-  static constexpr int RPL = TPI == 16 ? 4 : (TPI == 32 ? 2 : 1);   // row quads per lane
+  static constexpr int RPL = TPI == 16 ? ECG_UG_RPL16 : (TPI == 32 ? ECG_UG_RPL32 : 1);
   static constexpr int WROWS = 4 * RPL;                             // rows per wave step
   static constexpr int NWAVE = kThreads / 64;
   static constexpr int WGROWS = WROWS * NWAVE;                      // rows per WG step
@@ -88,53 +110,13 @@ __device__ double wg_sum(double v, double* lds_scratch) {
   return s;
 }
 
-// See RedCtl.  `red` (LDS, L doubles) holds this work-group's partial on
-// entry and, in the one work-group that returns true, the grid total.
-__device__ bool grid_reduce(double* red, int L, const RedCtl& rc) {
-  __shared__ int s_last;
-  const int tid = threadIdx.x;
-  const int G = gridDim.x, GS = rc.group_size;
-  const int g = blockIdx.x / GS;
-  const int ngroups = (G + GS - 1) / GS;
-  const int gsize = min(GS, G - g * GS);
+// Write this work-group's partial (LDS, L doubles) to rc.partials[blockIdx].
+// The totals are formed after the kernel by k_reduce_groups and k_final, so
+// no work-group waits for another and no device-scope fence is needed
+// inside the streaming kernels.
+__device__ void write_partial(const double* red, int L, const RedCtl& rc) {
   double* mine = rc.partials + (size_t)blockIdx.x * L;
-  for (int i = tid; i < L; i += blockDim.x) mine[i] = red[i];
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    unsigned prev = __hip_atomic_fetch_add(&rc.counters[g], 1u, __ATOMIC_ACQ_REL,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (prev == (unsigned)(gsize - 1));
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  double* gsum = rc.groups + (size_t)g * L;
-  const double* base = rc.partials + (size_t)g * GS * L;
-  for (int i = tid; i < L; i += blockDim.x) {
-    double acc = 0.0;
-    for (int w = 0; w < gsize; ++w) acc += base[(size_t)w * L + i];
-    gsum[i] = acc;
-  }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    rc.counters[g] = 0u;
-    unsigned prev = __hip_atomic_fetch_add(&rc.counters[ngroups], 1u, __ATOMIC_ACQ_REL,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (prev == (unsigned)(ngroups - 1));
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  for (int i = tid; i < L; i += blockDim.x) {
-    double acc = 0.0;
-    for (int q = 0; q < ngroups; ++q) acc += rc.groups[(size_t)q * L + i];
-    red[i] = acc;
-  }
-  if (tid == 0) rc.counters[ngroups] = 0u;
-  __syncthreads();
-  return true;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) mine[i] = red[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -322,10 +304,8 @@ __global__ __launch_bounds__(kThreads) void k_resid(const int32_t* __restrict__ 
   const double s = wg_sum(rr, red);
   if (threadIdx.x == 0) red[0] = s;
   __syncthreads();
-  if (grid_reduce(red, 1, rc) && threadIdx.x == 0) {
-    if (ta.which == 0) ta.status->rho = sqrt(red[0]);
-    else ta.status->rho_true = sqrt(red[0]);
-  }
+  write_partial(red, 1, rc);
+  (void)ta;
 }
 
 template <int TPI, typename S>
@@ -341,100 +321,120 @@ __global__ __launch_bounds__(kThreads) void k_tsplit(const double* __restrict__ 
   }
 }
 
-// out[r] = (ident0 ? X0[r] : 0) + sum_b X_b[r] C_b ; H_g = sum_r P_g[r]^t out[r]
-template <int TPI, typename S, int NU, int NG, bool IDENT0, bool WRITE, int TAIL>
+// out[r] = (ident0 ? X0[r] : 0) + sum_b X_b[r] C_b ; H_g = sum_r P_g[r]^t out[r].
+// P0X tells that P[0] is the same block as the first coefficient operand
+// (the first CGS pass of block m uses A U_{m-1} both ways); it is loaded once.
+template <int TPI, typename S, int NU, int NG, bool IDENT0, bool WRITE, int TAIL, bool P0X>
 __global__ __launch_bounds__(kThreads) void k_update_gram(UGArgs<S> a) {
   using C = Cfg<TPI>;
   constexpr int EPL = C::EPL, RPL = C::RPL, T2 = C::T2;
   constexpr int NCOEF = NU - (IDENT0 ? 1 : 0);
+  constexpr int NX = NU;                         // loaded update operands (incl. X0)
+  constexpr int NP = NG - (P0X ? 1 : 0);         // separately loaded Gram operands
+  constexpr int NLD = NX + NP;
   constexpr int BODY = NCOEF * T2;
-  constexpr int TAILSZ = (TAIL == TAIL_CGS) ? (NG + 2) * T2 : NG * T2;
+  constexpr int TAILSZ = NG * T2;
   constexpr int LDSN = (BODY > TAILSZ ? BODY : TAILSZ) > 1 ? (BODY > TAILSZ ? BODY : TAILSZ) : 1;
   __shared__ double lds[LDSN];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m = lane & 15, rq = lane >> 4;
 
-  // coefficient matrices into LDS
   for (int b = 0; b < NCOEF; ++b) {
     const double* src = a.C[b + (IDENT0 ? 1 : 0)];
     for (int idx = tid; idx < T2; idx += blockDim.x) lds[b * T2 + idx] = src[idx];
   }
   __syncthreads();
+  // volatile: read the coefficients from LDS where they are used instead of
+  // holding all of them in registers
+  const volatile double* Cv = lds;
 
   d4 acc[NG > 0 ? NG : 1][EPL][EPL];
   for (int g = 0; g < (NG > 0 ? NG : 1); ++g)
     for (int i = 0; i < EPL; ++i)
       for (int j = 0; j < EPL; ++j) acc[g][i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
+  const S* src[NLD];
+  for (int b = 0; b < NX; ++b) src[b] = a.X[b];
+  for (int g = 0; g < NP; ++g) src[NX + g] = a.P[g + (P0X ? 1 : 0)];
+
   const int64_t n = a.n;
-  for (int64_t step = blockIdx.x; step * C::WGROWS < n; step += gridDim.x) {
-    // keep the coefficient reads from LDS inside the loop (registers would
-    // not hold them for TPI >= 32, and hoisting lowers occupancy)
-    asm volatile("" ::: "memory");
+  // operands of one wave step: [operand][q][e], zero on rows >= n
+  auto load_step = [&](int64_t step, double (&v)[NLD][RPL][EPL]) {
     const int64_t row0 = step * C::WGROWS + wave * C::WROWS + rq;
-    int64_t rowc[RPL];     // clamped rows: loads stay in bounds, values are masked
-    bool ok[RPL];
     for (int q = 0; q < RPL; ++q) {
       const int64_t row = row0 + 4 * q;
-      ok[q] = row < n;
-      rowc[q] = ok[q] ? row : n - 1;
-    }
-    double xv[NCOEF > 0 ? NCOEF : 1][RPL][EPL];
-    for (int b = 0; b < NCOEF; ++b) {
-      const S* X = a.X[b + (IDENT0 ? 1 : 0)];
-      for (int q = 0; q < RPL; ++q)
+      const bool ok = row < n;
+      const int64_t rc = ok ? row : n - 1;
+      for (int b = 0; b < NLD; ++b)
         for (int e = 0; e < EPL; ++e) {
-          const double v = ld(X + rowc[q] * TPI + m + 16 * e);
-          xv[b][q][e] = ok[q] ? v : 0.0;
+          const double x = ld(src[b] + rc * TPI + m + 16 * e);
+          v[b][q][e] = ok ? x : 0.0;
         }
     }
+  };
+
+  constexpr bool PF = ECG_UG_PREFETCH != 0;
+  double cur[NLD][RPL][EPL], nxt[PF ? NLD : 1][RPL][EPL];
+  int64_t step = blockIdx.x;
+  bool have = step * C::WGROWS < n;
+  if (have) load_step(step, cur);
+  while (have) {
+    const int64_t nstep = step + gridDim.x;
+    const bool have_next = nstep * C::WGROWS < n;
+    if constexpr (PF) {
+      if (have_next) load_step(nstep, nxt);
+    }
+
     double o[RPL][EPL];
     for (int q = 0; q < RPL; ++q)
-      for (int e = 0; e < EPL; ++e) {
-        if constexpr (IDENT0) {
-          const double v = ld(a.X[0] + rowc[q] * TPI + m + 16 * e);
-          o[q][e] = ok[q] ? v : 0.0;
-        } else {
-          o[q][e] = 0.0;
-        }
-      }
+      for (int e = 0; e < EPL; ++e) o[q][e] = IDENT0 ? cur[0][q][e] : 0.0;
     static_for<NCOEF>([&](auto bc) {
       constexpr int b = decltype(bc)::value;
-      const double* Cs = lds + b * T2;
+      constexpr int xb = b + (IDENT0 ? 1 : 0);
       static_for<EPL>([&](auto ec) {
         constexpr int e2 = decltype(ec)::value;
         static_for<16>([&](auto nc) {
           constexpr int nn = decltype(nc)::value;
           const int k = 16 * e2 + nn;
           double cv[EPL];
-          for (int e = 0; e < EPL; ++e) cv[e] = Cs[k * TPI + m + 16 * e];
+          for (int e = 0; e < EPL; ++e) cv[e] = Cv[b * T2 + k * TPI + m + 16 * e];
           for (int q = 0; q < RPL; ++q)
             for (int e = 0; e < EPL; ++e)
-              o[q][e] = (nn == 0 && e == 0) ? fmac_bcast<nn, true>(o[q][e], xv[b][q][e2], cv[e])
-                                            : fmac_bcast<nn, false>(o[q][e], xv[b][q][e2], cv[e]);
+              o[q][e] = (nn == 0 && e == 0) ? fmac_bcast<nn, true>(o[q][e], cur[xb][q][e2], cv[e])
+                                            : fmac_bcast<nn, false>(o[q][e], cur[xb][q][e2], cv[e]);
         });
       });
     });
+    const int64_t row0 = step * C::WGROWS + wave * C::WROWS + rq;
     if constexpr (WRITE) {
-      for (int q = 0; q < RPL; ++q)
-        if (ok[q])
-          for (int e = 0; e < EPL; ++e)
-            a.out[rowc[q] * TPI + m + 16 * e] = static_cast<S>(o[q][e]);
-    }
-    if constexpr (NG > 0) {
-      for (int g = 0; g < NG; ++g) {
-        double pv[RPL][EPL];
-        for (int q = 0; q < RPL; ++q)
-          for (int e = 0; e < EPL; ++e) {
-            const double v = ld(a.P[g] + rowc[q] * TPI + m + 16 * e);
-            pv[q][e] = ok[q] ? v : 0.0;
-          }
-        for (int q = 0; q < RPL; ++q)
-          for (int i = 0; i < EPL; ++i)
-            for (int j = 0; j < EPL; ++j) acc[g][i][j] = mfma16(pv[q][i], o[q][j], acc[g][i][j]);
+      for (int q = 0; q < RPL; ++q) {
+        const int64_t row = row0 + 4 * q;
+        if (row < n)
+          for (int e = 0; e < EPL; ++e) a.out[row * TPI + m + 16 * e] = static_cast<S>(o[q][e]);
       }
     }
+    if constexpr (NG > 0) {
+      static_for<NG>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        constexpr int slot = (P0X && g == 0) ? 0 : NX + g - (P0X ? 1 : 0);
+        for (int q = 0; q < RPL; ++q)
+          for (int i = 0; i < EPL; ++i)
+            for (int j = 0; j < EPL; ++j)
+              acc[g][i][j] = mfma16(cur[slot][q][i], o[q][j], acc[g][i][j]);
+      });
+    }
+    if constexpr (PF) {
+      if (have_next) {
+        for (int b = 0; b < NLD; ++b)
+          for (int q = 0; q < RPL; ++q)
+            for (int e = 0; e < EPL; ++e) cur[b][q][e] = nxt[b][q][e];
+      }
+    } else {
+      if (have_next) load_step(nstep, cur);
+    }
+    step = nstep;
+    have = have_next;
   }
 
   if constexpr (NG > 0) {
@@ -452,23 +452,34 @@ __global__ __launch_bounds__(kThreads) void k_update_gram(UGArgs<S> a) {
       }
       __syncthreads();
     }
-    if (grid_reduce(lds, L, a.rc)) {
-      if (a.tail.sums_out)
-        for (int i = tid; i < L; i += blockDim.x) a.tail.sums_out[i] = lds[i];
-      if constexpr (TAIL == TAIL_CGS) tail_cgs<TPI>(lds, lds + L, NG, a.tail);
-    }
+    write_partial(lds, L, a.rc);
   }
 }
 
 // AZ = A Z (row by row) with the Gram epilogue G = Z^t AZ, F = AZ^t AZ,
-// E = AZprev^t AZ and a = Z^t r.
+// E = AZprev^t AZ and a = Z^t r.  The nonzeros of a row are gathered in
+// unrolled chunks of kChunk so that many independent loads are in flight.
+constexpr int kChunk = ECG_SP_CHUNK;
+constexpr int kSpCap = 1024;   // staged nonzeros per work-group step
+
+template <int TPI>
+struct SpCfg {
+  static constexpr int EPL = TPI / 16;
+  static constexpr int RPL = TPI == 16 ? ECG_SP_RPL16 : 1;
+  static constexpr int WROWS = 4 * RPL;
+  static constexpr int NWAVE = kThreads / 64;
+  static constexpr int WGROWS = WROWS * NWAVE;
+};
+
 template <int TPI, typename S, typename SA, bool GRAMS, bool HAS_PREV, int TAIL>
 __global__ __launch_bounds__(kThreads) void k_spmm(SpArgs<S, SA> a) {
-  using C = Cfg<TPI>;
-  constexpr int EPL = C::EPL, RPL = C::RPL, T2 = C::T2;
+  using C = SpCfg<TPI>;
+  constexpr int EPL = C::EPL, RPL = C::RPL, T2 = TPI * TPI;
   constexpr int L = 3 * T2 + TPI;
-  constexpr int LDSN = GRAMS ? (TAIL == TAIL_SPMM ? L + T2 : L) : 1;
+  constexpr int LDSN = GRAMS ? L : 1;
   __shared__ double lds[LDSN];
+  __shared__ int s_col[ECG_SP_LDS != 0 ? kSpCap : 1];
+  __shared__ SA s_val[ECG_SP_LDS != 0 ? kSpCap : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m = lane & 15, rq = lane >> 4;
 
@@ -483,36 +494,100 @@ __global__ __launch_bounds__(kThreads) void k_spmm(SpArgs<S, SA> a) {
     }
   }
   const int64_t n = a.n;
+  const int nnz_last = a.rowptr[n] - 1;
   for (int64_t step = blockIdx.x; step * C::WGROWS < n; step += gridDim.x) {
     const int64_t row0 = step * C::WGROWS + wave * C::WROWS + rq;
-    double y[RPL][EPL];
+    int64_t rowc[RPL];
+    bool ok[RPL];
+    int p0[RPL], p1[RPL];
+    int len = 0;
     for (int q = 0; q < RPL; ++q) {
       const int64_t row = row0 + 4 * q;
-      for (int e = 0; e < EPL; ++e) y[q][e] = 0.0;
-      if (row < n) {
-        const int p0 = a.rowptr[row], p1 = a.rowptr[row + 1];
-        for (int p = p0; p < p1; ++p) {
-          const int64_t col = a.colind[p];
-          const double v = static_cast<double>(a.vals[p]);
-          for (int e = 0; e < EPL; ++e)
-            y[q][e] = __builtin_fma(v, ld(a.Z + col * TPI + m + 16 * e), y[q][e]);
+      ok[q] = row < n;
+      rowc[q] = ok[q] ? row : n - 1;
+      p0[q] = a.rowptr[rowc[q]];
+      p1[q] = ok[q] ? a.rowptr[rowc[q] + 1] : p0[q];
+      len = max(len, p1[q] - p0[q]);
+    }
+    // operands of the Gram epilogue, independent of the product
+    double z[RPL][EPL], pz[RPL][EPL], rv[RPL];
+    if constexpr (GRAMS) {
+      for (int q = 0; q < RPL; ++q) {
+        const double r = a.rvec ? a.rvec[rowc[q]] : 0.0;
+        rv[q] = ok[q] ? r : 0.0;
+        for (int e = 0; e < EPL; ++e) {
+          const double zz = ld(a.Z + rowc[q] * TPI + m + 16 * e);
+          z[q][e] = ok[q] ? zz : 0.0;
+          if constexpr (HAS_PREV) {
+            const double pp = ld(a.AZprev + rowc[q] * TPI + m + 16 * e);
+            pz[q][e] = ok[q] ? pp : 0.0;
+          } else {
+            pz[q][e] = 0.0;
+          }
         }
-        for (int e = 0; e < EPL; ++e) a.AZ[row * TPI + m + 16 * e] = static_cast<S>(y[q][e]);
       }
     }
+    double y[RPL][EPL];
+    for (int q = 0; q < RPL; ++q)
+      for (int e = 0; e < EPL; ++e) y[q][e] = 0.0;
+    bool staged = false;
+    if constexpr (ECG_SP_LDS != 0) {
+      // the step's nonzeros are contiguous: stage colind / vals through LDS
+      // with coalesced loads when they fit
+      const int64_t r0 = step * C::WGROWS;
+      const int64_t r1 = min(r0 + C::WGROWS, n);
+      const int P0 = a.rowptr[r0], P1 = a.rowptr[r1];
+      if (P1 - P0 <= kSpCap) {
+        staged = true;
+        __syncthreads();
+        for (int i = tid; i < P1 - P0; i += blockDim.x) {
+          s_col[i] = a.colind[P0 + i];
+          s_val[i] = a.vals[P0 + i];
+        }
+        __syncthreads();
+        for (int c = 0; c < len; c += kChunk) {
+          for (int q = 0; q < RPL; ++q)
+            for (int j = 0; j < kChunk; ++j) {
+              const int idx = p0[q] + c + j;
+              const bool okj = idx < p1[q];
+              const int li = okj ? idx - P0 : 0;
+              const int col = okj ? s_col[li] : 0;
+              const double vv = okj ? static_cast<double>(s_val[li]) : 0.0;
+              for (int e = 0; e < EPL; ++e)
+                y[q][e] = __builtin_fma(vv, ld(a.Z + (int64_t)col * TPI + m + 16 * e), y[q][e]);
+            }
+        }
+      }
+    }
+    if (!staged) {
+      for (int c = 0; c < len; c += kChunk) {
+        int col[RPL][kChunk];
+        double v[RPL][kChunk];
+        for (int q = 0; q < RPL; ++q)
+          for (int j = 0; j < kChunk; ++j) {
+            const int idx = p0[q] + c + j;
+            const bool okj = idx < p1[q];
+            const int idc = min(idx, nnz_last);
+            col[q][j] = a.colind[idc];
+            const double vv = static_cast<double>(a.vals[idc]);
+            v[q][j] = okj ? vv : 0.0;
+          }
+        for (int q = 0; q < RPL; ++q)
+          for (int j = 0; j < kChunk; ++j)
+            for (int e = 0; e < EPL; ++e)
+              y[q][e] = __builtin_fma(v[q][j], ld(a.Z + (int64_t)col[q][j] * TPI + m + 16 * e),
+                                      y[q][e]);
+      }
+    }
+    for (int q = 0; q < RPL; ++q)
+      if (ok[q])
+        for (int e = 0; e < EPL; ++e) a.AZ[rowc[q] * TPI + m + 16 * e] = static_cast<S>(y[q][e]);
     if constexpr (GRAMS) {
-      double z[RPL][EPL], pz[RPL][EPL], rv[RPL];
       for (int q = 0; q < RPL; ++q) {
-        const int64_t row = row0 + 4 * q;
-        rv[q] = (row < n && a.rvec) ? a.rvec[row] : 0.0;
         for (int e = 0; e < EPL; ++e) {
           // the stored (rounded) value of AZ enters the Grams
           y[q][e] = static_cast<double>(static_cast<S>(y[q][e]));
-          z[q][e] = row < n ? ld(a.Z + row * TPI + m + 16 * e) : 0.0;
-          pz[q][e] = (HAS_PREV && row < n) ? ld(a.AZprev + row * TPI + m + 16 * e) : 0.0;
         }
-      }
-      for (int q = 0; q < RPL; ++q) {
         for (int i = 0; i < EPL; ++i) {
           av[i] = __builtin_fma(z[q][i], rv[q], av[i]);
           for (int j = 0; j < EPL; ++j) {
@@ -549,57 +624,68 @@ __global__ __launch_bounds__(kThreads) void k_spmm(SpArgs<S, SA> a) {
       }
       __syncthreads();
     }
-    if (grid_reduce(lds, L, a.rc)) {
-      if (a.tail.sums_out)
-        for (int i = tid; i < L; i += blockDim.x) a.tail.sums_out[i] = lds[i];
-      if constexpr (TAIL == TAIL_SPMM) tail_spmm<TPI>(lds, lds + L, a.tail);
-    }
+    write_partial(lds, L, a.rc);
   }
 }
 
-// x += sum_i U_i beta_i ; r -= sum_i AU_i beta_i ; ||r||^2
+// x += sum_i U_i beta_i ; r -= sum_i AU_i beta_i ; ||r||^2.  Blocks are
+// taken four at a time so that eight loads per row are in flight.
 template <int TPI, typename S>
 __global__ __launch_bounds__(kThreads) void k_xr(XRArgs<S> a) {
   constexpr int EPL = TPI / 16, RPL = 4, WROWS = 4 * RPL, NWAVE = kThreads / 64;
-  constexpr int WGROWS = WROWS * NWAVE;
+  constexpr int WGROWS = WROWS * NWAVE, NB4 = 4;
   __shared__ double bl[kMaxS * TPI];
   __shared__ double red[8];
   if (a.status_in->breakdown) return;     // uniform: the host stops after this iteration
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m = lane & 15, rq = lane >> 4;
-  for (int i = 0; i < a.nb; ++i)
-    for (int c = tid; c < TPI; c += blockDim.x) bl[i * TPI + c] = a.beta[i][c];
+  for (int i = 0; i < kMaxS; ++i)
+    for (int c = tid; c < TPI; c += blockDim.x) bl[i * TPI + c] = i < a.nb ? a.beta[i][c] : 0.0;
   __syncthreads();
   double rr = 0.0;
   const int64_t n = a.n;
   for (int64_t step = blockIdx.x; step * WGROWS < n; step += gridDim.x) {
     const int64_t row0 = step * WGROWS + wave * WROWS + rq;
+    int64_t rowc[RPL];
+    bool ok[RPL];
+    for (int q = 0; q < RPL; ++q) {
+      const int64_t row = row0 + 4 * q;
+      ok[q] = row < n;
+      rowc[q] = ok[q] ? row : n - 1;
+    }
     double dx[RPL], dr[RPL];
     for (int q = 0; q < RPL; ++q) {
       dx[q] = 0.0;
       dr[q] = 0.0;
     }
-    for (int i = 0; i < a.nb; ++i) {
-      for (int q = 0; q < RPL; ++q) {
-        const int64_t row = row0 + 4 * q;
-        if (row < n)
+    for (int i0 = 0; i0 < a.nb; i0 += NB4) {
+      double u[NB4][RPL][EPL], au[NB4][RPL][EPL];
+      for (int j = 0; j < NB4; ++j) {
+        const int i = min(i0 + j, a.nb - 1);   // past the end: beta is zero
+        for (int q = 0; q < RPL; ++q)
           for (int e = 0; e < EPL; ++e) {
-            const double bv = bl[i * TPI + m + 16 * e];
-            dx[q] = __builtin_fma(ld(a.U[i] + row * TPI + m + 16 * e), bv, dx[q]);
-            dr[q] = __builtin_fma(ld(a.AU[i] + row * TPI + m + 16 * e), bv, dr[q]);
+            u[j][q][e] = ld(a.U[i] + rowc[q] * TPI + m + 16 * e);
+            au[j][q][e] = ld(a.AU[i] + rowc[q] * TPI + m + 16 * e);
           }
       }
+      for (int j = 0; j < NB4; ++j)
+        for (int e = 0; e < EPL; ++e) {
+          const double bv = bl[(i0 + j) * TPI + m + 16 * e];
+          for (int q = 0; q < RPL; ++q) {
+            dx[q] = __builtin_fma(u[j][q][e], bv, dx[q]);
+            dr[q] = __builtin_fma(au[j][q][e], bv, dr[q]);
+          }
+        }
     }
     for (int q = 0; q < RPL; ++q) {
       for (int off = 8; off > 0; off >>= 1) {
         dx[q] += __shfl_xor(dx[q], off, 16);
         dr[q] += __shfl_xor(dr[q], off, 16);
       }
-      const int64_t row = row0 + 4 * q;
-      if (m == 0 && row < n) {
-        a.x[row] += dx[q];
-        const double rn = a.r[row] - dr[q];
-        a.r[row] = rn;
+      if (m == 0 && ok[q]) {
+        a.x[rowc[q]] += dx[q];
+        const double rn = a.r[rowc[q]] - dr[q];
+        a.r[rowc[q]] = rn;
         rr += rn * rn;
       }
     }
@@ -607,7 +693,7 @@ __global__ __launch_bounds__(kThreads) void k_xr(XRArgs<S> a) {
   const double s = wg_sum(rr, red);
   if (tid == 0) red[0] = s;
   __syncthreads();
-  if (grid_reduce(red, 1, a.rc) && tid == 0) a.tail.status->rho = sqrt(red[0]);
+  write_partial(red, 1, a.rc);
 }
 
 template <int TPI, typename S>
@@ -656,6 +742,62 @@ __global__ void k_unpack(const double* __restrict__ Xp, int TPI, double* __restr
   }
 }
 
+// Group sums: work-group (g, chunk) adds, for 256 consecutive entries, the
+// partials of producer work-groups g*GS .. g*GS + GS - 1 in index order.
+__global__ __launch_bounds__(kThreads) void k_reduce_groups(const double* __restrict__ partials,
+                                                            int G, int L, int GS,
+                                                            double* __restrict__ groups) {
+  const int chunks = (L + kThreads - 1) / kThreads;
+  const int g = blockIdx.x / chunks;
+  const int e = (blockIdx.x % chunks) * kThreads + threadIdx.x;
+  if (e >= L) return;
+  const int w0 = g * GS, w1 = min(G, w0 + GS);
+  const double* p = partials + (size_t)w0 * L + e;
+  double acc = 0.0;
+  int w = w0;
+  for (; w + 8 <= w1; w += 8) {
+    double v[8];
+    for (int j = 0; j < 8; ++j) v[j] = p[(size_t)(w - w0 + j) * L];
+    for (int j = 0; j < 8; ++j) acc += v[j];
+  }
+  for (; w < w1; ++w) acc += p[(size_t)(w - w0) * L];
+  groups[(size_t)g * L + e] = acc;
+}
+
+// Totals over the group sums (index order), then the small dense algebra.
+template <int TPI, int TAIL, int NG>
+__global__ __launch_bounds__(kThreads) void k_final(const double* __restrict__ groups,
+                                                    int ngroups, int L, TailArgs ta) {
+  constexpr int T2 = TPI * TPI;
+  constexpr int LSP = 3 * T2 + TPI;
+  constexpr int LDSN = TAIL == TAIL_SPMM ? LSP + T2 : (TAIL == TAIL_CGS ? (NG + 2) * T2 : 8);
+  __shared__ double lds[LDSN];
+  for (int i = threadIdx.x; i < L; i += blockDim.x) {
+    double acc = 0.0;
+    int q = 0;
+    for (; q + 8 <= ngroups; q += 8) {
+      double v[8];
+      for (int j = 0; j < 8; ++j) v[j] = groups[(size_t)(q + j) * L + i];
+      for (int j = 0; j < 8; ++j) acc += v[j];
+    }
+    for (; q < ngroups; ++q) acc += groups[(size_t)q * L + i];
+    lds[i] = acc;
+  }
+  __syncthreads();
+  if (ta.sums_out)
+    for (int i = threadIdx.x; i < L; i += blockDim.x) ta.sums_out[i] = lds[i];
+  if constexpr (TAIL == TAIL_SPMM) {
+    tail_spmm<TPI>(lds, lds + LSP, ta);
+  } else if constexpr (TAIL == TAIL_CGS) {
+    tail_cgs<TPI>(lds, lds + NG * T2, NG, ta);
+  } else if constexpr (TAIL == TAIL_NORM) {
+    if (threadIdx.x == 0) {
+      if (ta.which == 0) ta.status->rho = sqrt(lds[0]);
+      else ta.status->rho_true = sqrt(lds[0]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -665,6 +807,39 @@ static int simple_grid(int64_t work) {
   if (g > 4096) g = 4096;
   if (g < 1) g = 1;
   return (int)g;
+}
+
+hipError_t launch_reduce(const RedCtl& rc, int G, int L, int tpi, int tail, int ng,
+                         const TailArgs& ta, hipStream_t st) {
+  const int GS = rc.group_size;
+  const int ngroups = (G + GS - 1) / GS;
+  const int chunks = (L + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(k_reduce_groups, dim3(ngroups * chunks), dim3(kThreads), 0, st, rc.partials,
+                     G, L, GS, rc.groups);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+#define ECG_FIN(TPIV, TL, NGV)                                                               \
+  if (tpi == TPIV && tail == TL && ng == NGV) {                                              \
+    hipLaunchKernelGGL((k_final<TPIV, TL, NGV>), dim3(1), dim3(kThreads), 0, st, rc.groups,  \
+                       ngroups, L, ta);                                                      \
+    return hipGetLastError();                                                                \
+  }
+  if (tail == TAIL_NORM) {   // scalar tail: independent of the block width
+    hipLaunchKernelGGL((k_final<16, TAIL_NORM, 0>), dim3(1), dim3(kThreads), 0, st, rc.groups,
+                       ngroups, L, ta);
+    return hipGetLastError();
+  }
+  ECG_FIN(16, TAIL_SPMM, 0)
+  ECG_FIN(32, TAIL_SPMM, 0)
+  ECG_FIN(64, TAIL_SPMM, 0)
+  ECG_FIN(16, TAIL_CGS, 1)
+  ECG_FIN(32, TAIL_CGS, 1)
+  ECG_FIN(64, TAIL_CGS, 1)
+  ECG_FIN(16, TAIL_CGS, 2)
+  ECG_FIN(32, TAIL_CGS, 2)
+  ECG_FIN(64, TAIL_CGS, 2)
+#undef ECG_FIN
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_partition(int64_t nx, int64_t ny, int64_t nz, int px, int py, int pz,
@@ -694,18 +869,19 @@ hipError_t launch_tsplit(const double* r, const int32_t* dom, S* Z, int64_t n, i
 template <int TPI, typename S>
 hipError_t launch_update_gram(int nu, int ng, bool ident0, bool write_out, int tail,
                               const UGArgs<S>& a, int grid, hipStream_t st) {
-#define ECG_UG(NU, NG, ID, WR, TL)                                                        \
-  if (nu == NU && ng == NG && ident0 == ID && write_out == WR && tail == TL) {             \
-    hipLaunchKernelGGL((k_update_gram<TPI, S, NU, NG, ID, WR, TL>), dim3(grid),           \
-                       dim3(kThreads), 0, st, a);                                         \
-    return hipGetLastError();                                                             \
+#define ECG_UG(NU, NG, ID, WR, TL, P0X)                                                   \
+  if (nu == NU && ng == NG && ident0 == ID && write_out == WR && tail == TL &&             \
+      (a.P[0] == a.X[0]) == P0X) {                                                         \
+    hipLaunchKernelGGL((k_update_gram<TPI, S, NU, NG, ID, WR, TL, P0X>), dim3(grid),       \
+                       dim3(kThreads), 0, st, a);                                          \
+    return hipGetLastError();                                                              \
   }
   // first CGS pass of blocks m = 2 and m >= 3 (fused with the second Gram)
-  ECG_UG(2, 1, false, true, TAIL_CGS)
-  ECG_UG(3, 2, false, true, TAIL_CGS)
+  ECG_UG(2, 1, false, true, TAIL_CGS, true)
+  ECG_UG(3, 2, false, true, TAIL_CGS, true)
   // second CGS pass
-  ECG_UG(2, 0, true, true, TAIL_NONE)
-  ECG_UG(3, 0, true, true, TAIL_NONE)
+  ECG_UG(2, 0, true, true, TAIL_NONE, false)
+  ECG_UG(3, 0, true, true, TAIL_NONE, false)
 #undef ECG_UG
   return hipErrorInvalidValue;
 }

@@ -49,7 +49,7 @@ int fail(int code, const std::string& msg) {
   } while (0)
 
 const char* kclass_names[ECG_K_COUNT] = {"resid",  "tsplit", "cgs_gram", "cgs_update", "spmm",
-                                         "xr_update", "gram", "update", "other"};
+                                         "xr_update", "gram", "update", "small"};
 
 struct Timed {
   int k;
@@ -90,7 +90,6 @@ struct ecg_ctx {
 
   double* partials = nullptr;
   double* groups = nullptr;
-  unsigned* counters = nullptr;
   int grid = 1024;
   int group_size = 32;
 
@@ -103,7 +102,7 @@ struct ecg_ctx {
   std::vector<hipEvent_t> free_events;
   hipEvent_t ev_solve0 = nullptr, ev_solve1 = nullptr;
 
-  RedCtl rc() const { return RedCtl{partials, groups, counters, group_size}; }
+  RedCtl rc() const { return RedCtl{partials, groups, group_size}; }
   int T2() const { return tpi * tpi; }
   double blk_bytes() const { return (double)n * t * sbytes; }
   double csr_bytes(int vb) const { return (double)nnz * (vb + 4) + 4.0 * (n + 1); }
@@ -240,7 +239,7 @@ int dalloc(T** p, size_t count, size_t& total) {
 
 int pick_tpi(int t) { return t <= 16 ? 16 : (t <= 32 ? 32 : 64); }
 
-int rows_per_wg(int tpi) { return tpi == 16 ? 64 : (tpi == 32 ? 32 : 16); }
+int rows_per_wg(int) { return 64; }
 
 }  // namespace
 
@@ -255,7 +254,7 @@ extern "C" void ecg_destroy(ecg_ctx* c) {
   for (void* p : c->AU) f(p);
   f(c->Zp); f(c->rinv); f(c->beta); f(c->cnext); f(c->dcoef);
   f(c->scratch); f(c->scratch2); f(c->status);
-  f(c->partials); f(c->groups); f(c->counters);
+  f(c->partials); f(c->groups);
   if (c->h_status) (void)hipHostFree(c->h_status);
   for (auto& tm : c->pending) {
     (void)hipEventDestroy(tm.a);
@@ -423,7 +422,6 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   ALLOC(c->status, DevStatus, 1);
   ALLOC(c->partials, double, (size_t)max_grid * L);
   ALLOC(c->groups, double, (size_t)ngroups * L);
-  ALLOC(c->counters, unsigned, (size_t)ngroups + 1);
 #undef ALLOC
   if (hipHostMalloc((void**)&c->h_status, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(ECG_ENOMEM, "pinned host allocation failed"));
@@ -454,8 +452,7 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
       hipMemsetAsync(c->beta, 0, sizeof(double) * c->nslot * tpi, c->st) != hipSuccess ||
       hipMemsetAsync(c->cnext, 0, sizeof(double) * 3 * T2, c->st) != hipSuccess ||
       hipMemsetAsync(c->dcoef, 0, sizeof(double) * 2 * T2, c->st) != hipSuccess ||
-      hipMemsetAsync(c->status, 0, sizeof(DevStatus), c->st) != hipSuccess ||
-      hipMemsetAsync(c->counters, 0, sizeof(unsigned) * (ngroups + 1), c->st) != hipSuccess)
+      hipMemsetAsync(c->status, 0, sizeof(DevStatus), c->st) != hipSuccess)
     return cleanup(fail(ECG_EDEVICE, "workspace clear failed"));
   if (hipEventCreate(&c->ev_solve0) != hipSuccess || hipEventCreate(&c->ev_solve1) != hipSuccess)
     return cleanup(fail(ECG_EDEVICE, "event creation failed"));
@@ -493,16 +490,27 @@ struct Engine {
     return ta;
   }
 
+  // totals of the partials of the last producer (G work-groups, L values)
+  // and the small algebra `tail`
+  int reduce(int G, int L, int tail, int ng, const TailArgs& ta) {
+    Timed tm;
+    c->tstart(tm, ECG_K_SMALL, 8.0 * G * L + 8.0 * ((G + c->group_size - 1) / c->group_size) * L,
+              (double)G * L);
+    HIP_TRY(launch_reduce(c->rc(), G, L, TPI, tail, ng, ta, c->st));
+    c->tstop(tm);
+    return ECG_OK;
+  }
+
   int resid(int which) {
     TailArgs ta = tail0(0);
     ta.which = which;
     Timed tm;
     c->tstart(tm, ECG_K_RESID, c->csr_bytes(8) + 24.0 * c->n, 2.0 * c->nnz + 3.0 * c->n);
-    const int g = (int)std::min<int64_t>((c->n + kThreads - 1) / kThreads, 1024);
+    const int g = (int)std::min<int64_t>((c->n + kThreads - 1) / kThreads, c->grid);
     HIP_TRY(launch_resid(c->rowptr, c->colind, c->vals, c->b, c->x, c->r, c->n, g, c->rc(), ta,
                          c->st));
     c->tstop(tm);
-    return ECG_OK;
+    return reduce(g, 1, TAIL_NORM, 0, ta);
   }
 
   // Build block m (1-based since the last restart) into `slot`; p1, p2 are
@@ -536,6 +544,8 @@ struct Engine {
       c->tstart(tm, ECG_K_CGS_GRAM, (2.0 * np + 1.0) * bb, 2.0 * nt2 * (2 * np + 1 + np));
       HIP_TRY((launch_update_gram<TPI, S>(np + 1, np, false, true, TAIL_CGS, ka, c->grid, c->st)));
       c->tstop(tm);
+      int rc = reduce(c->grid, np * TPI * TPI, TAIL_CGS, np, ka.tail);
+      if (rc) return rc;
 
       UGArgs<S> kb{};
       kb.X[0] = (const S*)c->Zp;
@@ -572,7 +582,7 @@ struct Engine {
               2.0 * c->nnz * c->t + 2.0 * nt2 * (m >= 2 ? 3 : 2) + 2.0 * c->n * c->t);
     HIP_TRY((launch_spmm<TPI, S, SA>(true, m >= 2, TAIL_SPMM, sa, c->grid, c->st)));
     c->tstop(tm);
-    return ECG_OK;
+    return reduce(c->grid, 3 * TPI * TPI + TPI, TAIL_SPMM, 0, sa.tail);
   }
 
   int xr(const int* slots, int nb) {
@@ -592,10 +602,10 @@ struct Engine {
     Timed tm;
     c->tstart(tm, ECG_K_XR_UPDATE, 2.0 * nb * c->blk_bytes() + 32.0 * c->n,
               4.0 * nb * (double)c->n * c->t + 2.0 * c->n);
-    const int g = (int)std::min<int64_t>((c->n + 63) / 64, 1024);
+    const int g = (int)std::min<int64_t>((c->n + 63) / 64, c->grid);
     HIP_TRY((launch_xr<TPI, S>(xa, g, c->st)));
     c->tstop(tm);
-    return ECG_OK;
+    return reduce(g, 1, TAIL_NORM, 0, xa.tail);
   }
 
   int read_status(DevStatus* h) {
