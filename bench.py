@@ -95,6 +95,27 @@ def cpu_baseline(p, gpu_iters, budget_iters=1):
     }
 
 
+def calibrate(torch):
+    """Plain device copy of 256 MiB: the practical streaming ceiling, and the
+    known-size kernel against which FETCH_SIZE / WRITE_SIZE are scaled."""
+    n = 1 << 25
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 20
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"calibration": "copy", "bytes_read": 8 * n, "bytes_written": 8 * n,
+                      "us_per_copy": round(ms * 1e3, 1),
+                      "gbs": round(16 * n / (ms * 1e-3) / 1e9, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +125,8 @@ def main():
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="time a plain 256 MiB device copy (the reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
@@ -114,6 +137,9 @@ def main():
     import paper_1804_10629_amd as E
 
     torch.cuda.set_device(0)
+    if args.calibrate:
+        calibrate(torch)
+        return
     t0 = time.perf_counter()
     p = build_problem(args.config)
     log(f"problem {p.name}: n={p.n} nnz={p.nnz} t={p.t} s={p.s} ({time.perf_counter() - t0:.1f} s)")

@@ -55,6 +55,12 @@ __device__ __forceinline__ double fmac_bcast(double acc, double x, double c) {
   return acc;
 }
 
+// Value of lane (16 * (lane / 16) + N) of a 64-bit register (DPP row_newbcast).
+template <int N>
+__device__ __forceinline__ double bcast64(double v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x150 + N, 0xF, 0xF, true);
+}
+
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -75,14 +81,23 @@ __device__ __forceinline__ double ld(const S* p) { return static_cast<double>(*p
 #define ECG_UG_PREFETCH 0
 #endif
 #ifndef ECG_SP_RPL16
-#define ECG_SP_RPL16 2
+#define ECG_SP_RPL16 4
 #endif
+#ifndef ECG_XCD_MAP
+#define ECG_XCD_MAP 1
+#endif
+// Occupancy the streaming kernels are scheduled for (waves per SIMD).  The
+// launches give each CU a few work-groups of four waves, so the compiler is
+// told not to trade memory-level parallelism (loads kept in flight) for an
+// occupancy the grid never reaches.
+#ifndef ECG_WAVES_PER_EU
+#define ECG_WAVES_PER_EU 2
+#endif
+#define ECG_STREAM __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ECG_WAVES_PER_EU, ECG_WAVES_PER_EU)))
 #ifndef ECG_SP_CHUNK
 #define ECG_SP_CHUNK 8
 #endif
-#ifndef ECG_SP_LDS
-#define ECG_SP_LDS 0
-#endif
+
 
 template <int TPI>
 struct Cfg {
@@ -93,6 +108,26 @@ struct Cfg {
   static constexpr int WGROWS = WROWS * NWAVE;                      // rows per WG step
   static constexpr int T2 = TPI * TPI;
 };
+
+// Row steps of a work-group.  Work-groups are dispatched to the 8 XCDs of the
+// device in round-robin order and each XCD has its own L2, so each XCD gets
+// a contiguous range of steps (its work-groups sweep that range together):
+// the neighbours a sparse row reaches (+-1, +-nx, +-nx*ny rows on a grid)
+// were then fetched by the same XCD shortly before.
+struct Steps {
+  int64_t first, end, stride;
+};
+
+__device__ __forceinline__ Steps my_steps(int64_t nsteps) {
+  const int G = gridDim.x;
+  if (ECG_XCD_MAP && G % 8 == 0 && G >= 64) {
+    const int xcd = blockIdx.x % 8, local = blockIdx.x / 8, per = G / 8;
+    const int64_t sx = (nsteps + 7) / 8;
+    const int64_t b = xcd * sx;
+    return Steps{b + local, min(nsteps, b + sx), per};
+  }
+  return Steps{blockIdx.x, nsteps, G};
+}
 
 // ---------------------------------------------------------------------------
 // Work-group and grid reductions
@@ -284,7 +319,7 @@ __global__ void k_partition(int64_t nx, int64_t ny, int64_t nz, int px, int py, 
 }
 
 // r = b - A x ; sums: ||r||^2
-__global__ __launch_bounds__(kThreads) void k_resid(const int32_t* __restrict__ rowptr,
+__global__ ECG_STREAM void k_resid(const int32_t* __restrict__ rowptr,
                                                     const int32_t* __restrict__ colind,
                                                     const double* __restrict__ vals,
                                                     const double* __restrict__ b,
@@ -325,7 +360,7 @@ __global__ __launch_bounds__(kThreads) void k_tsplit(const double* __restrict__ 
 // P0X tells that P[0] is the same block as the first coefficient operand
 // (the first CGS pass of block m uses A U_{m-1} both ways); it is loaded once.
 template <int TPI, typename S, int NU, int NG, bool IDENT0, bool WRITE, int TAIL, bool P0X>
-__global__ __launch_bounds__(kThreads) void k_update_gram(UGArgs<S> a) {
+__global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
   using C = Cfg<TPI>;
   constexpr int EPL = C::EPL, RPL = C::RPL, T2 = C::T2;
   constexpr int NCOEF = NU - (IDENT0 ? 1 : 0);
@@ -376,12 +411,13 @@ __global__ __launch_bounds__(kThreads) void k_update_gram(UGArgs<S> a) {
 
   constexpr bool PF = ECG_UG_PREFETCH != 0;
   double cur[NLD][RPL][EPL], nxt[PF ? NLD : 1][RPL][EPL];
-  int64_t step = blockIdx.x;
-  bool have = step * C::WGROWS < n;
+  const Steps sp = my_steps((n + C::WGROWS - 1) / C::WGROWS);
+  int64_t step = sp.first;
+  bool have = step < sp.end;
   if (have) load_step(step, cur);
   while (have) {
-    const int64_t nstep = step + gridDim.x;
-    const bool have_next = nstep * C::WGROWS < n;
+    const int64_t nstep = step + sp.stride;
+    const bool have_next = nstep < sp.end;
     if constexpr (PF) {
       if (have_next) load_step(nstep, nxt);
     }
@@ -457,29 +493,25 @@ __global__ __launch_bounds__(kThreads) void k_update_gram(UGArgs<S> a) {
 }
 
 // AZ = A Z (row by row) with the Gram epilogue G = Z^t AZ, F = AZ^t AZ,
-// E = AZprev^t AZ and a = Z^t r.  The nonzeros of a row are gathered in
-// unrolled chunks of kChunk so that many independent loads are in flight.
-constexpr int kChunk = ECG_SP_CHUNK;
-constexpr int kSpCap = 1024;   // staged nonzeros per work-group step
+// E = AZprev^t AZ and a = Z^t r.
+constexpr int kChunk = ECG_SP_CHUNK;   // <= 16
 
 template <int TPI>
 struct SpCfg {
   static constexpr int EPL = TPI / 16;
-  static constexpr int RPL = TPI == 16 ? ECG_SP_RPL16 : 1;
+  static constexpr int RPL = TPI == 16 ? ECG_SP_RPL16 : (TPI == 32 ? 2 : 1);
   static constexpr int WROWS = 4 * RPL;
   static constexpr int NWAVE = kThreads / 64;
   static constexpr int WGROWS = WROWS * NWAVE;
 };
 
 template <int TPI, typename S, typename SA, bool GRAMS, bool HAS_PREV, int TAIL>
-__global__ __launch_bounds__(kThreads) void k_spmm(SpArgs<S, SA> a) {
+__global__ ECG_STREAM void k_spmm(SpArgs<S, SA> a) {
   using C = SpCfg<TPI>;
   constexpr int EPL = C::EPL, RPL = C::RPL, T2 = TPI * TPI;
   constexpr int L = 3 * T2 + TPI;
   constexpr int LDSN = GRAMS ? L : 1;
   __shared__ double lds[LDSN];
-  __shared__ int s_col[ECG_SP_LDS != 0 ? kSpCap : 1];
-  __shared__ SA s_val[ECG_SP_LDS != 0 ? kSpCap : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m = lane & 15, rq = lane >> 4;
 
@@ -495,19 +527,76 @@ __global__ __launch_bounds__(kThreads) void k_spmm(SpArgs<S, SA> a) {
   }
   const int64_t n = a.n;
   const int nnz_last = a.rowptr[n] - 1;
-  for (int64_t step = blockIdx.x; step * C::WGROWS < n; step += gridDim.x) {
+  const Steps sp = my_steps((n + C::WGROWS - 1) / C::WGROWS);
+
+  // Software pipeline over the wave's steps: while the rows of step i are
+  // gathered, the first kChunk (column, value) pairs of step i+1 and the
+  // row pointers of step i+2 are in flight, so a step waits on one memory
+  // round trip instead of three dependent ones.
+  struct RowPtr {
+    int p0[RPL], p1[RPL];
+  };
+  struct Head {                 // first chunk of every row: lane m holds entry m % kChunk
+    double offb[RPL], valb[RPL];
+  };
+  auto load_rowptr = [&](int64_t step, RowPtr& rp) {
+    const int64_t row0 = step * C::WGROWS + wave * C::WROWS + rq;
+    for (int q = 0; q < RPL; ++q) {
+      const int64_t row = row0 + 4 * q;
+      const int64_t rc = row < n ? row : n - 1;
+      rp.p0[q] = a.rowptr[rc];
+      const int pe = a.rowptr[rc + 1];
+      rp.p1[q] = row < n ? pe : rp.p0[q];
+    }
+  };
+  auto load_chunk = [&](const RowPtr& rp, int c, Head& h) {
+    for (int q = 0; q < RPL; ++q) {
+      const int idx = rp.p0[q] + c + (m % kChunk);
+      const bool okm = idx < rp.p1[q];
+      const int idc = min(idx, nnz_last);
+      const int64_t col = a.colind[idc];
+      const double vv = static_cast<double>(a.vals[idc]);
+      h.offb[q] = __builtin_bit_cast(double, (int64_t)(okm ? col * TPI : 0));
+      h.valb[q] = okm ? vv : 0.0;
+    }
+  };
+  auto gather = [&](const Head& h, double (&y)[RPL][EPL]) {
+    static_for<kChunk>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      for (int q = 0; q < RPL; ++q) {
+        const int64_t off = __builtin_bit_cast(int64_t, bcast64<j>(h.offb[q]));
+        const double vj = bcast64<j>(h.valb[q]);
+        const S* zr = a.Z + off + m;
+        for (int e = 0; e < EPL; ++e) y[q][e] = __builtin_fma(vj, ld(zr + 16 * e), y[q][e]);
+      }
+    });
+  };
+
+  RowPtr rp_cur, rp_nxt;
+  Head h_cur;
+  int64_t step = sp.first;
+  if (step < sp.end) {
+    load_rowptr(step, rp_cur);
+    load_chunk(rp_cur, 0, h_cur);
+    if (step + sp.stride < sp.end) load_rowptr(step + sp.stride, rp_nxt);
+  }
+  for (; step < sp.end; step += sp.stride) {
+    const int64_t s1 = step + sp.stride, s2 = s1 + sp.stride;
+    const bool has1 = s1 < sp.end, has2 = s2 < sp.end;
+    Head h_nxt;
+    RowPtr rp_nn;
+    if (has1) load_chunk(rp_nxt, 0, h_nxt);
+    if (has2) load_rowptr(s2, rp_nn);
+
     const int64_t row0 = step * C::WGROWS + wave * C::WROWS + rq;
     int64_t rowc[RPL];
     bool ok[RPL];
-    int p0[RPL], p1[RPL];
     int len = 0;
     for (int q = 0; q < RPL; ++q) {
       const int64_t row = row0 + 4 * q;
       ok[q] = row < n;
       rowc[q] = ok[q] ? row : n - 1;
-      p0[q] = a.rowptr[rowc[q]];
-      p1[q] = ok[q] ? a.rowptr[rowc[q] + 1] : p0[q];
-      len = max(len, p1[q] - p0[q]);
+      len = max(len, rp_cur.p1[q] - rp_cur.p0[q]);
     }
     // operands of the Gram epilogue, independent of the product
     double z[RPL][EPL], pz[RPL][EPL], rv[RPL];
@@ -530,54 +619,11 @@ __global__ __launch_bounds__(kThreads) void k_spmm(SpArgs<S, SA> a) {
     double y[RPL][EPL];
     for (int q = 0; q < RPL; ++q)
       for (int e = 0; e < EPL; ++e) y[q][e] = 0.0;
-    bool staged = false;
-    if constexpr (ECG_SP_LDS != 0) {
-      // the step's nonzeros are contiguous: stage colind / vals through LDS
-      // with coalesced loads when they fit
-      const int64_t r0 = step * C::WGROWS;
-      const int64_t r1 = min(r0 + C::WGROWS, n);
-      const int P0 = a.rowptr[r0], P1 = a.rowptr[r1];
-      if (P1 - P0 <= kSpCap) {
-        staged = true;
-        __syncthreads();
-        for (int i = tid; i < P1 - P0; i += blockDim.x) {
-          s_col[i] = a.colind[P0 + i];
-          s_val[i] = a.vals[P0 + i];
-        }
-        __syncthreads();
-        for (int c = 0; c < len; c += kChunk) {
-          for (int q = 0; q < RPL; ++q)
-            for (int j = 0; j < kChunk; ++j) {
-              const int idx = p0[q] + c + j;
-              const bool okj = idx < p1[q];
-              const int li = okj ? idx - P0 : 0;
-              const int col = okj ? s_col[li] : 0;
-              const double vv = okj ? static_cast<double>(s_val[li]) : 0.0;
-              for (int e = 0; e < EPL; ++e)
-                y[q][e] = __builtin_fma(vv, ld(a.Z + (int64_t)col * TPI + m + 16 * e), y[q][e]);
-            }
-        }
-      }
-    }
-    if (!staged) {
-      for (int c = 0; c < len; c += kChunk) {
-        int col[RPL][kChunk];
-        double v[RPL][kChunk];
-        for (int q = 0; q < RPL; ++q)
-          for (int j = 0; j < kChunk; ++j) {
-            const int idx = p0[q] + c + j;
-            const bool okj = idx < p1[q];
-            const int idc = min(idx, nnz_last);
-            col[q][j] = a.colind[idc];
-            const double vv = static_cast<double>(a.vals[idc]);
-            v[q][j] = okj ? vv : 0.0;
-          }
-        for (int q = 0; q < RPL; ++q)
-          for (int j = 0; j < kChunk; ++j)
-            for (int e = 0; e < EPL; ++e)
-              y[q][e] = __builtin_fma(v[q][j], ld(a.Z + (int64_t)col[q][j] * TPI + m + 16 * e),
-                                      y[q][e]);
-      }
+    gather(h_cur, y);
+    for (int c = kChunk; c < len; c += kChunk) {   // rows longer than one chunk
+      Head h;
+      load_chunk(rp_cur, c, h);
+      gather(h, y);
     }
     for (int q = 0; q < RPL; ++q)
       if (ok[q])
@@ -598,6 +644,11 @@ __global__ __launch_bounds__(kThreads) void k_spmm(SpArgs<S, SA> a) {
         }
       }
     }
+    if (has1) {
+      h_cur = h_nxt;
+      rp_cur = rp_nxt;
+    }
+    if (has2) rp_nxt = rp_nn;
   }
   if constexpr (GRAMS) {
     // a: reduce over the four row lanes of each column, then over waves
@@ -631,7 +682,7 @@ __global__ __launch_bounds__(kThreads) void k_spmm(SpArgs<S, SA> a) {
 // x += sum_i U_i beta_i ; r -= sum_i AU_i beta_i ; ||r||^2.  Blocks are
 // taken four at a time so that eight loads per row are in flight.
 template <int TPI, typename S>
-__global__ __launch_bounds__(kThreads) void k_xr(XRArgs<S> a) {
+__global__ ECG_STREAM void k_xr(XRArgs<S> a) {
   constexpr int EPL = TPI / 16, RPL = 4, WROWS = 4 * RPL, NWAVE = kThreads / 64;
   constexpr int WGROWS = WROWS * NWAVE, NB4 = 4;
   __shared__ double bl[kMaxS * TPI];
@@ -644,7 +695,8 @@ __global__ __launch_bounds__(kThreads) void k_xr(XRArgs<S> a) {
   __syncthreads();
   double rr = 0.0;
   const int64_t n = a.n;
-  for (int64_t step = blockIdx.x; step * WGROWS < n; step += gridDim.x) {
+  const Steps sp = my_steps((n + WGROWS - 1) / WGROWS);
+  for (int64_t step = sp.first; step < sp.end; step += sp.stride) {
     const int64_t row0 = step * WGROWS + wave * WROWS + rq;
     int64_t rowc[RPL];
     bool ok[RPL];
@@ -772,16 +824,26 @@ __global__ __launch_bounds__(kThreads) void k_final(const double* __restrict__ g
   constexpr int LSP = 3 * T2 + TPI;
   constexpr int LDSN = TAIL == TAIL_SPMM ? LSP + T2 : (TAIL == TAIL_CGS ? (NG + 2) * T2 : 8);
   __shared__ double lds[LDSN];
-  for (int i = threadIdx.x; i < L; i += blockDim.x) {
-    double acc = 0.0;
-    int q = 0;
-    for (; q + 8 <= ngroups; q += 8) {
-      double v[8];
-      for (int j = 0; j < 8; ++j) v[j] = groups[(size_t)(q + j) * L + i];
-      for (int j = 0; j < 8; ++j) acc += v[j];
+  // entries four at a time, group sums sixteen at a time: up to 64 loads in
+  // flight per thread; each entry is still summed in group order
+  constexpr int NE = 4, NQ = 16;
+  for (int i0 = threadIdx.x; i0 < L; i0 += NE * blockDim.x) {
+    double acc[NE];
+    for (int u = 0; u < NE; ++u) acc[u] = 0.0;
+    for (int q = 0; q < ngroups; q += NQ) {
+      double v[NE][NQ];
+      for (int u = 0; u < NE; ++u) {
+        const int i = min(i0 + u * (int)blockDim.x, L - 1);
+        for (int j = 0; j < NQ; ++j) v[u][j] = groups[(size_t)min(q + j, ngroups - 1) * L + i];
+      }
+      for (int u = 0; u < NE; ++u)
+        for (int j = 0; j < NQ; ++j)
+          if (q + j < ngroups) acc[u] += v[u][j];
     }
-    for (; q < ngroups; ++q) acc += groups[(size_t)q * L + i];
-    lds[i] = acc;
+    for (int u = 0; u < NE; ++u) {
+      const int i = i0 + u * (int)blockDim.x;
+      if (i < L) lds[i] = acc[u];
+    }
   }
   __syncthreads();
   if (ta.sums_out)
