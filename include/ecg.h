@@ -74,8 +74,10 @@ typedef struct ecg_opts {
                              at the last restart (default 1e-5; ignored in
                              ECG_FP64) */
   int32_t max_restarts;   /* bound on residual replacements (default 20) */
-  int32_t q_cap_blocks;   /* ECG_SRECG2: stored blocks before a forced restart;
-                             0 = as many as ws_cap_bytes allows (default 0) */
+  int32_t q_cap_blocks;   /* ECG_SRECG2: blocks kept since the last restart; when
+                             another s would exceed it the solve restarts from
+                             x.  0 = as many as ws_cap_bytes allows, at most
+                             2048; otherwise at least s (default 0) */
   int64_t ws_cap_bytes;   /* device workspace cap; 0 = 90% of free memory */
   void*   hip_stream;     /* hipStream_t to run on; NULL = null stream */
   int32_t collect_stats;  /* 1: time every kernel with HIP events (ecg_last_stats) */
@@ -149,12 +151,13 @@ int ecg_partition_grid(int64_t nx, int64_t ny, int64_t nz, int32_t px, int32_t p
  * Create a solver for the n x n SPD matrix (rowptr, colind, vals) with the
  * t domains partition[i] in [0, t) and s blocks per iteration.
  * Copies everything to device memory and allocates the workspace: (s+2)
- * pairs of n x t blocks (basis W and its A-image) for ECG_SRECG, up to
- * q_cap_blocks pairs for ECG_SRECG2, plus scratch.
+ * pairs of n x t blocks (basis W and its A-image) for ECG_SRECG, one pair
+ * per kept block (q_cap_blocks) for ECG_SRECG2, plus scratch.
  * Errors: ECG_EINVAL (out == NULL; n <= 0; t < 1; t > 64; t > n; s < 1;
  * rowptr not starting at 0 or decreasing; nnz >= 2^31; a column index out
  * of [0, n); a partition value out of [0, t); an empty domain; a
- * non-finite value; nonzero reserved fields), ECG_ENOMEM (the workspace
+ * non-finite value; nonzero reserved fields; ECG_SRECG2 with q_cap_blocks
+ * in [1, s)), ECG_ENOMEM (the workspace
  * does not fit ws_cap_bytes or device memory), ECG_EDEVICE.  Symmetry and
  * definiteness are not checked here; an indefinite matrix is reported by
  * ecg_solve as ECG_BREAKDOWN.  On error *out is NULL.

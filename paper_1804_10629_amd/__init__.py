@@ -241,7 +241,9 @@ class Solver:
             x = torch.zeros(self.n, dtype=torch.float64, device="cuda")
         else:
             x = _dev_tensor(x0, torch.float64).clone()
-        cap = maxit + 2 + 2 * (self.opts.max_restarts + 1)
+        # rho_0, one norm per iteration, one per restart (residual replacements
+        # are bounded by max_restarts, SRE-CG2 block-cap restarts by maxit)
+        cap = 2 * maxit + self.opts.max_restarts + 4
         hist = np.zeros(cap, dtype=np.float64)
         res = _Result()
         code = lib.ecg_solve(self._ctx, bd.data_ptr(), x.data_ptr(), float(tol), int(maxit),

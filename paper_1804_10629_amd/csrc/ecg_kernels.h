@@ -43,9 +43,22 @@ struct TailArgs {
   DevStatus* status;
   double* sums_out;            // copy of the reduced sums (nullable)
   int which;                   // TAIL_NORM: 0 -> status.rho, 1 -> status.rho_true
+  // TAIL_GRAM: for the Grams G_g of one chunk (g < ng),
+  //   coef_out[g] = -R_g^{-1} R_g^{-t} G_g (R_right^{-1} if rinv_right)
+  const double* rinv_g[3];
+  double* coef_out[3];
+  const double* rinv_right;
+  // TAIL_PRE: Cholesky of the Euclidean Gram; R^{-1} to coef_out[0]
 };
 
-enum TailKind { TAIL_NONE = 0, TAIL_SPMM = 1, TAIL_CGS = 2, TAIL_NORM = 3, TAIL_PRE = 4 };
+enum TailKind {
+  TAIL_NONE = 0,
+  TAIL_SPMM = 1,   // A-CholQR of the new block + next first-pass coefficients
+  TAIL_CGS = 2,    // second-pass coefficients against the previous two blocks
+  TAIL_NORM = 3,   // a residual norm
+  TAIL_PRE = 4,    // Euclidean CholQR factor (Pre-CholQR)
+  TAIL_GRAM = 5    // coefficients for one chunk of earlier blocks (SRE-CG2)
+};
 
 template <typename S>
 struct UGArgs {

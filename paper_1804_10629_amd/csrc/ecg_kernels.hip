@@ -214,7 +214,8 @@ __device__ void trinv_upper_inplace(double* R, int t, double* tmp) {
 }
 
 // C = op(A) B on the leading t x t blocks (op = transpose if ta); the
-// padding of C is zero.  C may live in global memory; A, B in LDS.
+// padding of C is zero.  Operands normally live in LDS; any of them may be
+// in global memory.
 template <int TPI>
 __device__ void small_mm(const double* A, bool ta, const double* B, double* C, int t,
                          double scale) {
@@ -300,6 +301,42 @@ __device__ void tail_cgs(double* sums, double* tmp, int ng, const TailArgs& ta) 
     copy_mat<TPI>(g == 0 ? ta.rinv_p1 : ta.rinv_p2, Rs);
     small_mm<TPI>(Rs, true, sums + g * T2, T, ta.t, 1.0);
     small_mm<TPI>(Rs, false, T, ta.dcoef + g * T2, ta.t, -1.0);
+  }
+}
+
+// Tail for one chunk of earlier blocks (SRE-CG2): sums hold G_g (g < ng);
+// coef_out[g] = -R_g^{-1} (R_g^{-t} G_g [R_right^{-1}]).
+template <int TPI>
+__device__ void tail_gram(double* sums, double* tmp, int ng, const TailArgs& ta) {
+  constexpr int T2 = TPI * TPI;
+  double* Rs = tmp;
+  double* T = tmp + T2;
+  for (int g = 0; g < ng; ++g) {
+    copy_mat<TPI>(ta.rinv_g[g], Rs);
+    small_mm<TPI>(Rs, true, sums + g * T2, T, ta.t, 1.0);      // T = R_g^{-t} G_g
+    if (ta.rinv_right) {
+      // G_g <- T R_right^{-1} (the right factor is read from global memory)
+      small_mm<TPI>(T, false, ta.rinv_right, sums + g * T2, ta.t, 1.0);
+      small_mm<TPI>(Rs, false, sums + g * T2, ta.coef_out[g], ta.t, -1.0);
+    } else {
+      small_mm<TPI>(Rs, false, T, ta.coef_out[g], ta.t, -1.0);
+    }
+  }
+}
+
+// Tail of Pre-CholQR: the Euclidean Gram Z^t Z = Re^t Re; Re^{-1} to
+// coef_out[0] (breakdown as for A-CholQR).
+template <int TPI>
+__device__ void tail_pre(double* sums, double* tmp, const TailArgs& ta) {
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  chol_upper_inplace<TPI>(sums, ta.t, &s_bad);
+  trinv_upper_inplace<TPI>(sums, ta.t, tmp);
+  for (int idx = threadIdx.x; idx < TPI * TPI; idx += blockDim.x) ta.coef_out[0][idx] = sums[idx];
+  if (threadIdx.x == 0 && s_bad && ta.status->breakdown == 0) {
+    ta.status->breakdown = 1;
+    ta.status->breakdown_block = ta.m;
   }
 }
 
@@ -822,7 +859,9 @@ __global__ __launch_bounds__(kThreads) void k_final(const double* __restrict__ g
                                                     int ngroups, int L, TailArgs ta) {
   constexpr int T2 = TPI * TPI;
   constexpr int LSP = 3 * T2 + TPI;
-  constexpr int LDSN = TAIL == TAIL_SPMM ? LSP + T2 : (TAIL == TAIL_CGS ? (NG + 2) * T2 : 8);
+  constexpr int LDSN = TAIL == TAIL_SPMM ? LSP + T2
+                       : (TAIL == TAIL_CGS ? (NG + 2) * T2
+                       : (TAIL == TAIL_GRAM ? (NG + 2) * T2 : (TAIL == TAIL_PRE ? 2 * T2 : 8)));
   __shared__ double lds[LDSN];
   // entries four at a time, group sums sixteen at a time: up to 64 loads in
   // flight per thread; each entry is still summed in group order
@@ -852,6 +891,10 @@ __global__ __launch_bounds__(kThreads) void k_final(const double* __restrict__ g
     tail_spmm<TPI>(lds, lds + LSP, ta);
   } else if constexpr (TAIL == TAIL_CGS) {
     tail_cgs<TPI>(lds, lds + NG * T2, NG, ta);
+  } else if constexpr (TAIL == TAIL_GRAM) {
+    tail_gram<TPI>(lds, lds + NG * T2, NG, ta);
+  } else if constexpr (TAIL == TAIL_PRE) {
+    tail_pre<TPI>(lds, lds + T2, ta);
   } else if constexpr (TAIL == TAIL_NORM) {
     if (threadIdx.x == 0) {
       if (ta.which == 0) ta.status->rho = sqrt(lds[0]);
@@ -900,6 +943,17 @@ hipError_t launch_reduce(const RedCtl& rc, int G, int L, int tpi, int tail, int 
   ECG_FIN(16, TAIL_CGS, 2)
   ECG_FIN(32, TAIL_CGS, 2)
   ECG_FIN(64, TAIL_CGS, 2)
+  ECG_FIN(16, TAIL_GRAM, 1)
+  ECG_FIN(16, TAIL_GRAM, 2)
+  ECG_FIN(16, TAIL_GRAM, 3)
+  ECG_FIN(32, TAIL_GRAM, 1)
+  ECG_FIN(32, TAIL_GRAM, 2)
+  ECG_FIN(32, TAIL_GRAM, 3)
+  ECG_FIN(64, TAIL_GRAM, 1)
+  ECG_FIN(64, TAIL_GRAM, 2)
+  ECG_FIN(16, TAIL_PRE, 1)
+  ECG_FIN(32, TAIL_PRE, 1)
+  ECG_FIN(64, TAIL_PRE, 1)
 #undef ECG_FIN
   return hipErrorInvalidValue;
 }
@@ -944,6 +998,16 @@ hipError_t launch_update_gram(int nu, int ng, bool ident0, bool write_out, int t
   // second CGS pass
   ECG_UG(2, 0, true, true, TAIL_NONE, false)
   ECG_UG(3, 0, true, true, TAIL_NONE, false)
+  // SRE-CG2 chunks: first update chunk, in-place update chunks, Gram chunks
+  ECG_UG(3, 0, false, true, TAIL_NONE, false)
+  ECG_UG(2, 0, false, true, TAIL_NONE, false)
+  ECG_UG(4, 0, true, true, TAIL_NONE, false)
+  ECG_UG(1, 1, true, false, TAIL_NONE, false)
+  ECG_UG(1, 2, true, false, TAIL_NONE, false)
+  ECG_UG(1, 3, true, false, TAIL_NONE, false)
+  // Pre-CholQR: Euclidean Gram of a block with itself, and the scaling
+  ECG_UG(1, 1, true, false, TAIL_NONE, true)
+  ECG_UG(1, 0, false, true, TAIL_NONE, false)
 #undef ECG_UG
   return hipErrorInvalidValue;
 }

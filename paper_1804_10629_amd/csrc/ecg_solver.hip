@@ -76,13 +76,17 @@ struct ecg_ctx {
   double* x = nullptr;
   double* r = nullptr;
 
-  int nslot = 0;
+  int nslot = 0;              // block slots (SRE-CG2: the block cap)
+  int nalloc = 0;             // slots with allocated U / AU
   std::vector<void*> U, AU;
   void* Zp = nullptr;
   double* rinv = nullptr;     // [nslot][T2]
   double* beta = nullptr;     // [nslot][tpi]
   double* cnext = nullptr;    // [3][T2]
   double* dcoef = nullptr;    // [2][T2]
+  double* ctab = nullptr;     // SRE-CG2: [nslot][T2] first-pass coefficients
+  double* dtab = nullptr;     // SRE-CG2: [nslot][T2] second-pass coefficients
+  double* pre_rinv = nullptr; // Pre-CholQR: Re^{-1}
   double* scratch = nullptr;  // op buffers (n * tpi doubles, lazily)
   double* scratch2 = nullptr;
   DevStatus* status = nullptr;
@@ -253,6 +257,7 @@ extern "C" void ecg_destroy(ecg_ctx* c) {
   for (void* p : c->U) f(p);
   for (void* p : c->AU) f(p);
   f(c->Zp); f(c->rinv); f(c->beta); f(c->cnext); f(c->dcoef);
+  f(c->ctab); f(c->dtab); f(c->pre_rinv);
   f(c->scratch); f(c->scratch2); f(c->status);
   f(c->partials); f(c->groups);
   if (c->h_status) (void)hipHostFree(c->h_status);
@@ -282,6 +287,28 @@ extern "C" int ecg_partition_grid(int64_t nx, int64_t ny, int64_t nz, int32_t px
   return ECG_OK;
 }
 
+// Allocate and zero block pairs up to `want` slots (padding columns of a
+// block stay zero from here on).  On failure the slots allocated so far
+// stay usable and ECG_ENOMEM is returned.
+static int grow_slots(ecg_ctx* c, int want) {
+  const size_t bytes = (size_t)c->n * c->tpi * c->sbytes;
+  for (int i = c->nalloc; i < want; ++i) {
+    void *u = nullptr, *au = nullptr;
+    if (hipMalloc(&u, bytes) != hipSuccess) return fail(ECG_ENOMEM, "block allocation failed");
+    if (hipMalloc(&au, bytes) != hipSuccess) {
+      (void)hipFree(u);
+      return fail(ECG_ENOMEM, "block allocation failed");
+    }
+    c->U[i] = u;
+    c->AU[i] = au;
+    if (hipMemsetAsync(u, 0, bytes, c->st) != hipSuccess ||
+        hipMemsetAsync(au, 0, bytes, c->st) != hipSuccess)
+      return fail(ECG_EDEVICE, "block clear failed");
+    c->nalloc = i + 1;
+  }
+  return ECG_OK;
+}
+
 extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const int32_t* colind,
                          const double* vals, const int32_t* partition, int32_t t, int32_t s,
                          const ecg_opts* opts) {
@@ -305,8 +332,8 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   if (!(o.inner_tol >= 0.0 && o.inner_tol < 1.0)) return fail(ECG_EINVAL, "inner_tol must be in [0, 1)");
   if (o.max_restarts < 0 || o.q_cap_blocks < 0 || o.ws_cap_bytes < 0 || o.grid < 0)
     return fail(ECG_EINVAL, "negative option");
-  if (o.variant == ECG_SRECG2) return fail(ECG_ENOTSUP, "SRE-CG2 is not available in this build");
-  if (o.orth == ECG_PRECHOLQR) return fail(ECG_ENOTSUP, "Pre-CholQR is not available in this build");
+  if (o.variant == ECG_SRECG2 && o.q_cap_blocks > 0 && o.q_cap_blocks < s)
+    return fail(ECG_EINVAL, "q_cap_blocks must be 0 or at least s");
   const bool dev = o.device_ptrs == 1;
   if (dev) {
     int rc = check_device();
@@ -370,14 +397,29 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   const size_t L = 3 * (size_t)T2 + tpi;
 
   // ---- workspace size check ----
-  c->nslot = s + 2;
   const size_t esz = c->sbytes;
-  double need = 2.0 * c->nslot * blk * esz + blk * esz + (double)nnz * (4 + 8 + (o.precision ? 4 : 0)) +
-                4.0 * (n + 1) + 4.0 * n + 3.0 * 8 * n + (double)max_grid * L * 8 +
-                (double)ngroups * L * 8;
+  const double fixed = blk * esz + (double)nnz * (4 + 8 + (o.precision ? 4 : 0)) +
+                       4.0 * (n + 1) + 4.0 * n + 3.0 * 8 * n + (double)max_grid * L * 8 +
+                       (double)ngroups * L * 8;
+  const double per_slot = 2.0 * blk * esz + 8.0 * (3.0 * T2 + tpi);
   size_t freeb = 0, totalb = 0;
   HIP_TRY(hipMemGetInfo(&freeb, &totalb));
   double cap = o.ws_cap_bytes > 0 ? (double)o.ws_cap_bytes : 0.9 * (double)freeb;
+  if (o.variant == ECG_SRECG2) {
+    // every block since the last restart is kept: one slot per block, at
+    // least the s blocks of one iteration
+    int64_t fit = (int64_t)((cap - fixed) / per_slot);
+    int64_t want = o.q_cap_blocks > 0 ? o.q_cap_blocks : std::min<int64_t>(fit, 2048);
+    if (want < s || want > fit) {
+      delete c;
+      return fail(ECG_ENOMEM, "SRE-CG2 workspace: " + std::to_string(want) + " blocks requested, " +
+                                  std::to_string(fit) + " fit, at least s needed");
+    }
+    c->nslot = (int)want;
+  } else {
+    c->nslot = s + 2;
+  }
+  double need = fixed + per_slot * c->nslot;
   if (need > cap) {
     delete c;
     return fail(ECG_ENOMEM, "workspace of " + std::to_string(need) + " bytes exceeds the cap of " +
@@ -402,16 +444,13 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   ALLOC(c->x, double, n);
   ALLOC(c->r, double, n);
   if (o.precision == ECG_MIXED) ALLOC(c->vals32, float, nnz);
+  // SRE-CG2 keeps one block pair per block since the last restart; its
+  // pairs are allocated when a solve first needs them (grow_slots)
   c->U.assign(c->nslot, nullptr);
   c->AU.assign(c->nslot, nullptr);
-  for (int i = 0; i < c->nslot; ++i) {
-    if (o.precision == ECG_MIXED) {
-      ALLOC(*(float**)&c->U[i], float, blk);
-      ALLOC(*(float**)&c->AU[i], float, blk);
-    } else {
-      ALLOC(*(double**)&c->U[i], double, blk);
-      ALLOC(*(double**)&c->AU[i], double, blk);
-    }
+  {
+    const int first = o.variant == ECG_SRECG2 ? std::min(c->nslot, s + 2) : c->nslot;
+    if ((rc = grow_slots(c, first))) return cleanup(rc);
   }
   if (o.precision == ECG_MIXED) ALLOC(*(float**)&c->Zp, float, blk);
   else ALLOC(*(double**)&c->Zp, double, blk);
@@ -419,6 +458,11 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   ALLOC(c->beta, double, (size_t)c->nslot * tpi);
   ALLOC(c->cnext, double, 3 * (size_t)T2);
   ALLOC(c->dcoef, double, 2 * (size_t)T2);
+  ALLOC(c->pre_rinv, double, (size_t)T2);
+  if (o.variant == ECG_SRECG2) {
+    ALLOC(c->ctab, double, (size_t)c->nslot * T2);
+    ALLOC(c->dtab, double, (size_t)c->nslot * T2);
+  }
   ALLOC(c->status, DevStatus, 1);
   ALLOC(c->partials, double, (size_t)max_grid * L);
   ALLOC(c->groups, double, (size_t)ngroups * L);
@@ -442,11 +486,6 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
       return cleanup(fail(ECG_EDEVICE, "upload of binary32 values failed"));
   }
   // zero everything the kernels read before writing (padding columns stay zero)
-  for (int i = 0; i < c->nslot; ++i) {
-    if (hipMemsetAsync(c->U[i], 0, blk * esz, c->st) != hipSuccess ||
-        hipMemsetAsync(c->AU[i], 0, blk * esz, c->st) != hipSuccess)
-      return cleanup(fail(ECG_EDEVICE, "workspace clear failed"));
-  }
   if (hipMemsetAsync(c->Zp, 0, blk * esz, c->st) != hipSuccess ||
       hipMemsetAsync(c->rinv, 0, sizeof(double) * c->nslot * T2, c->st) != hipSuccess ||
       hipMemsetAsync(c->beta, 0, sizeof(double) * c->nslot * tpi, c->st) != hipSuccess ||
@@ -513,12 +552,144 @@ struct Engine {
     return reduce(g, 1, TAIL_NORM, 0, ta);
   }
 
+  // One launch of the generic update/Gram kernel, timed as class k.
+  int ug(int k, int nu, int ng, bool ident0, bool write, const UGArgs<S>& a, double bytes,
+         double flops) {
+    Timed tm;
+    c->tstart(tm, k, bytes, flops);
+    HIP_TRY((launch_update_gram<TPI, S>(nu, ng, ident0, write, TAIL_NONE, a, c->grid, c->st)));
+    c->tstop(tm);
+    return ECG_OK;
+  }
+
+  // SRE-CG2 (Algorithm "s-step SRE-CG2"): CGS2 of block m against every
+  // block since the last restart, slots 0 .. m-2 (block p in slot p-1), in
+  // chunks of at most CH earlier blocks per launch.  Blocks m-1 and m-2 take
+  // their first-pass coefficients from the product tail of block m-1, the
+  // older ones from Gram chunks against A U_{m-1}.
+  int cgs_all(int m, int slot) {
+    constexpr int T2 = TPI * TPI;
+    constexpr int CH = TPI == 64 ? 2 : 3;
+    const double bb = c->blk_bytes();
+    const double nt2 = (double)c->n * c->t * c->t;
+    const int newest = m - 2;                     // slot of block m-1
+    int rc;
+    // (a) first-pass Grams G_p = (A U_p)^t A U_{m-1} for blocks p <= m-3
+    for (int p0 = 0; p0 <= m - 4; p0 += CH) {
+      const int len = std::min(CH, m - 3 - p0);
+      UGArgs<S> g{};
+      g.X[0] = AU(newest);
+      for (int k = 0; k < len; ++k) g.P[k] = AU(p0 + k);
+      g.n = c->n;
+      g.rc = c->rc();
+      if ((rc = ug(ECG_K_GRAM, 1, len, true, false, g, (1.0 + len) * bb, 2.0 * nt2 * len)))
+        return rc;
+      TailArgs ta = tail0(m);
+      for (int k = 0; k < len; ++k) {
+        ta.rinv_g[k] = rinv(p0 + k);
+        ta.coef_out[k] = c->ctab + (size_t)(p0 + k) * T2;
+      }
+      ta.rinv_right = rinv(newest);
+      if ((rc = reduce(c->grid, len * T2, TAIL_GRAM, len, ta))) return rc;
+    }
+    // (b) first update: Z' = A U_{m-1} C0 + U_{m-1} C1 + U_{m-2} C2 + sum_p U_p C_p
+    {
+      UGArgs<S> u{};
+      u.X[0] = AU(newest);
+      u.X[1] = U(newest);
+      u.X[2] = U(newest - 1);
+      u.C[0] = c->cnext;
+      u.C[1] = c->cnext + T2;
+      u.C[2] = c->cnext + 2 * T2;
+      u.out = (S*)c->Zp;
+      u.n = c->n;
+      u.rc = c->rc();
+      if ((rc = ug(ECG_K_UPDATE, 3, 0, false, true, u, 4.0 * bb, 6.0 * nt2))) return rc;
+    }
+    for (int p0 = 0; p0 <= m - 4; p0 += CH) {
+      const int len = std::min(CH, m - 3 - p0);
+      UGArgs<S> u{};
+      u.X[0] = (const S*)c->Zp;
+      for (int k = 0; k < len; ++k) {
+        u.X[1 + k] = U(p0 + k);
+        u.C[1 + k] = c->ctab + (size_t)(p0 + k) * T2;
+      }
+      u.out = (S*)c->Zp;
+      u.n = c->n;
+      u.rc = c->rc();
+      if ((rc = ug(ECG_K_UPDATE, 1 + len, 0, true, true, u, (2.0 + len) * bb, 2.0 * nt2 * len)))
+        return rc;
+    }
+    // (c) second-pass Grams H2'_p = (A U_p)^t Z' for every earlier block
+    for (int p0 = 0; p0 <= m - 2; p0 += CH) {
+      const int len = std::min(CH, m - 1 - p0);
+      UGArgs<S> g{};
+      g.X[0] = (const S*)c->Zp;
+      for (int k = 0; k < len; ++k) g.P[k] = AU(p0 + k);
+      g.n = c->n;
+      g.rc = c->rc();
+      if ((rc = ug(ECG_K_GRAM, 1, len, true, false, g, (1.0 + len) * bb, 2.0 * nt2 * len)))
+        return rc;
+      TailArgs ta = tail0(m);
+      for (int k = 0; k < len; ++k) {
+        ta.rinv_g[k] = rinv(p0 + k);
+        ta.coef_out[k] = c->dtab + (size_t)(p0 + k) * T2;
+      }
+      ta.rinv_right = nullptr;
+      if ((rc = reduce(c->grid, len * T2, TAIL_GRAM, len, ta))) return rc;
+    }
+    // (d) second update: U_m = Z' + sum_p U_p D_p (in place after the first chunk)
+    for (int p0 = 0; p0 <= m - 2; p0 += CH) {
+      const int len = std::min(CH, m - 1 - p0);
+      UGArgs<S> u{};
+      u.X[0] = p0 == 0 ? (const S*)c->Zp : U(slot);
+      for (int k = 0; k < len; ++k) {
+        u.X[1 + k] = U(p0 + k);
+        u.C[1 + k] = c->dtab + (size_t)(p0 + k) * T2;
+      }
+      u.out = U(slot);
+      u.n = c->n;
+      u.rc = c->rc();
+      if ((rc = ug(ECG_K_UPDATE, 1 + len, 0, true, true, u, (2.0 + len) * bb, 2.0 * nt2 * len)))
+        return rc;
+    }
+    return ECG_OK;
+  }
+
+  // Pre-CholQR: Euclidean CholQR of the block before A-CholQR,
+  // U <- U Re^{-1} with U^t U = Re^t Re.
+  int pre_cholqr(int m, int slot) {
+    constexpr int T2 = TPI * TPI;
+    const double bb = c->blk_bytes();
+    const double nt2 = (double)c->n * c->t * c->t;
+    UGArgs<S> g{};
+    g.X[0] = U(slot);
+    g.P[0] = U(slot);
+    g.n = c->n;
+    g.rc = c->rc();
+    int rc = ug(ECG_K_GRAM, 1, 1, true, false, g, bb, 2.0 * nt2);
+    if (rc) return rc;
+    TailArgs ta = tail0(m);
+    ta.coef_out[0] = c->pre_rinv;
+    if ((rc = reduce(c->grid, T2, TAIL_PRE, 1, ta))) return rc;
+    UGArgs<S> u{};
+    u.X[0] = U(slot);
+    u.C[0] = c->pre_rinv;
+    u.out = U(slot);
+    u.n = c->n;
+    u.rc = c->rc();
+    return ug(ECG_K_UPDATE, 1, 0, false, true, u, 2.0 * bb, 2.0 * nt2);
+  }
+
   // Build block m (1-based since the last restart) into `slot`; p1, p2 are
   // the slots of blocks m-1 and m-2.
   int block(int m, int slot, int p1, int p2) {
     const double bb = c->blk_bytes();
     const double nt2 = (double)c->n * c->t * c->t;
-    if (m == 1) {
+    if (c->o.variant == ECG_SRECG2 && m >= 4) {
+      int rc = cgs_all(m, slot);
+      if (rc) return rc;
+    } else if (m == 1) {
       Timed tm;
       c->tstart(tm, ECG_K_TSPLIT, bb + 12.0 * c->n, 0.0);
       HIP_TRY((launch_tsplit<TPI, S>(c->r, c->dom, U(slot), c->n, c->grid, c->st)));
@@ -561,6 +732,10 @@ struct Engine {
       c->tstart(tm2, ECG_K_CGS_UPDATE, (np + 2.0) * bb, 2.0 * nt2 * np);
       HIP_TRY((launch_update_gram<TPI, S>(np + 1, 0, true, true, TAIL_NONE, kb, c->grid, c->st)));
       c->tstop(tm2);
+    }
+    if (c->o.orth == ECG_PRECHOLQR) {
+      int rc = pre_cholqr(m, slot);
+      if (rc) return rc;
     }
     SpArgs<S, SA> sa{};
     sa.rowptr = c->rowptr;
@@ -641,16 +816,36 @@ struct Engine {
     double rho = rho0, rho_restart = rho0;
     int k = 0, restarts = 0, m = 0, nblocks = 0;
     int status = ECG_OK;
-    const int ns = c->nslot;
+    int ns = c->nslot;
+    const bool cg2 = c->o.variant == ECG_SRECG2;
     int slot_of[3] = {-1, -1, -1};   // slots of blocks m, m-1, m-2
     bool have_basis = false;
     while (true) {
       const double thr = std::max(inner * rho_restart, thr_final);
       while (rho > thr && k < maxit) {
+        if (cg2 && m + c->s > c->nalloc && c->nalloc < ns) {
+          // more block pairs: on allocation failure the blocks held so far
+          // become the cap
+          const int g = grow_slots(c, std::min(ns, m + c->s));
+          if (g == ECG_ENOMEM) ns = c->nalloc;   // >= s from setup
+          else if (g) return g;
+        }
+        if (cg2 && m > 0 && m + c->s > ns) {
+          // every slot holds a block since the last restart: restart from x
+          if ((rc = resid(1))) return rc;
+          if ((rc = read_status(&h))) return rc;
+          rho = h.rho_true;
+          push(rho);
+          ++restarts;
+          rho_restart = rho;
+          m = 0;
+          slot_of[0] = slot_of[1] = slot_of[2] = -1;
+          continue;
+        }
         int slots[kMaxS];
         for (int i = 0; i < c->s; ++i) {
           ++m;
-          const int slot = (nblocks) % ns;
+          const int slot = cg2 ? m - 1 : nblocks % ns;
           slot_of[2] = slot_of[1];
           slot_of[1] = slot_of[0];
           slot_of[0] = slot;

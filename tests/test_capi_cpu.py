@@ -71,7 +71,7 @@ def small():
 
 @pytest.mark.parametrize("case", [
     "n0", "t0", "t65", "t_gt_n", "s0", "s17", "rowptr0", "decreasing", "col_range",
-    "part_range", "empty_domain", "nan_value", "reserved", "variant", "inner_tol"])
+    "part_range", "empty_domain", "nan_value", "reserved", "variant", "inner_tol", "q_cap"])
 def test_setup_rejects(small, case):
     p, dom = small
     rp, ci, va, pd = p.rowptr.copy(), p.colind.copy(), p.vals.copy(), dom.copy()
@@ -107,6 +107,8 @@ def test_setup_rejects(small, case):
         kw = {"variant": 7}
     elif case == "inner_tol":
         kw = {"inner_tol": 1.5}
+    elif case == "q_cap":
+        kw = {"variant": E.SRECG2, "q_cap_blocks": 1}
     code, msg = _setup(n, rp, ci, va, pd, t, s, **kw)
     assert code == E.EINVAL, (case, code, msg)
     assert msg
