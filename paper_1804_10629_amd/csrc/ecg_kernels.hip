@@ -68,6 +68,16 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
 template <typename S>
 __device__ __forceinline__ double ld(const S* p) { return static_cast<double>(*p); }
 
+// A value the optimiser cannot see through.  Masks built from row bounds go
+// through it, so that `loaded * mask` stays an arithmetic use of the load:
+// written as a select, the compiler sinks the load into a branch and waits
+// on all outstanding loads before it, which serialises the memory pipeline.
+template <typename T>
+__device__ __forceinline__ T opaque(T v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
 // Tuning knobs (compile-time): row quads per lane of the block-update
 // kernels at TPI = 16 / 32, prefetch of the next step's operands, row quads
 // per lane and gather chunk of the product kernel.
@@ -94,6 +104,31 @@ __device__ __forceinline__ double ld(const S* p) { return static_cast<double>(*p
 #define ECG_WAVES_PER_EU 2
 #endif
 #define ECG_STREAM __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ECG_WAVES_PER_EU, ECG_WAVES_PER_EU)))
+#ifndef ECG_SP_WPE
+#define ECG_SP_WPE ECG_WAVES_PER_EU
+#endif
+#define ECG_SPMM_ATTR __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ECG_SP_WPE, ECG_SP_WPE)))
+#ifndef ECG_SP_NT
+#define ECG_SP_NT 1            // streaming (non-temporal) access to A, r, A Z_prev and A Z
+#endif
+
+// Loads and stores of data used once (CSR arrays, streamed blocks): with
+// ECG_SP_NT they carry the non-temporal hint so that they do not displace
+// the gathered block from the caches.
+template <typename T>
+__device__ __forceinline__ T ld_s(const T* p) {
+  if constexpr (ECG_SP_NT != 0) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <typename T>
+__device__ __forceinline__ void st_s(T* p, T v) {
+  if constexpr (ECG_SP_NT != 0) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+#ifndef ECG_UG_CGROUP
+#define ECG_UG_CGROUP 4        // coefficient rows read from LDS per group (divides 16)
+#endif
 #ifndef ECG_SP_CHUNK
 #define ECG_SP_CHUNK 8
 #endif
@@ -417,9 +452,6 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
     for (int idx = tid; idx < T2; idx += blockDim.x) lds[b * T2 + idx] = src[idx];
   }
   __syncthreads();
-  // volatile: read the coefficients from LDS where they are used instead of
-  // holding all of them in registers
-  const volatile double* Cv = lds;
 
   d4 acc[NG > 0 ? NG : 1][EPL][EPL];
   for (int g = 0; g < (NG > 0 ? NG : 1); ++g)
@@ -436,13 +468,10 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
     const int64_t row0 = step * C::WGROWS + wave * C::WROWS + rq;
     for (int q = 0; q < RPL; ++q) {
       const int64_t row = row0 + 4 * q;
-      const bool ok = row < n;
-      const int64_t rc = ok ? row : n - 1;
+      const int64_t rc = row < n ? row : n - 1;
+      const double okf = opaque(row < n ? 1.0 : 0.0);
       for (int b = 0; b < NLD; ++b)
-        for (int e = 0; e < EPL; ++e) {
-          const double x = ld(src[b] + rc * TPI + m + 16 * e);
-          v[b][q][e] = ok ? x : 0.0;
-        }
+        for (int e = 0; e < EPL; ++e) v[b][q][e] = ld(src[b] + rc * TPI + m + 16 * e) * okf;
     }
   };
 
@@ -462,20 +491,32 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
     double o[RPL][EPL];
     for (int q = 0; q < RPL; ++q)
       for (int e = 0; e < EPL; ++e) o[q][e] = IDENT0 ? cur[0][q][e] : 0.0;
+    // Coefficient rows come from LDS (ds_read) in groups of CG: the empty
+    // asm with a memory clobber keeps the compiler from hoisting the
+    // loop-invariant reads out of the row loop, which would need all
+    // NCOEF * TPI * EPL values in registers.
+    constexpr int CG = ECG_UG_CGROUP;
     static_for<NCOEF>([&](auto bc) {
       constexpr int b = decltype(bc)::value;
       constexpr int xb = b + (IDENT0 ? 1 : 0);
       static_for<EPL>([&](auto ec) {
         constexpr int e2 = decltype(ec)::value;
-        static_for<16>([&](auto nc) {
-          constexpr int nn = decltype(nc)::value;
-          const int k = 16 * e2 + nn;
-          double cv[EPL];
-          for (int e = 0; e < EPL; ++e) cv[e] = Cv[b * T2 + k * TPI + m + 16 * e];
-          for (int q = 0; q < RPL; ++q)
+        static_for<16 / CG>([&](auto gc) {
+          constexpr int g0 = CG * decltype(gc)::value;
+          asm volatile("" ::: "memory");
+          double cv[CG][EPL];
+          for (int u = 0; u < CG; ++u)
             for (int e = 0; e < EPL; ++e)
-              o[q][e] = (nn == 0 && e == 0) ? fmac_bcast<nn, true>(o[q][e], cur[xb][q][e2], cv[e])
-                                            : fmac_bcast<nn, false>(o[q][e], cur[xb][q][e2], cv[e]);
+              cv[u][e] = lds[b * T2 + (16 * e2 + g0 + u) * TPI + m + 16 * e];
+          static_for<CG>([&](auto uc) {
+            constexpr int u = decltype(uc)::value;
+            constexpr int nn = g0 + u;
+            for (int q = 0; q < RPL; ++q)
+              for (int e = 0; e < EPL; ++e)
+                o[q][e] = (nn == 0 && e == 0)
+                              ? fmac_bcast<nn, true>(o[q][e], cur[xb][q][e2], cv[u][e])
+                              : fmac_bcast<nn, false>(o[q][e], cur[xb][q][e2], cv[u][e]);
+          });
         });
       });
     });
@@ -543,7 +584,7 @@ struct SpCfg {
 };
 
 template <int TPI, typename S, typename SA, bool GRAMS, bool HAS_PREV, int TAIL>
-__global__ ECG_STREAM void k_spmm(SpArgs<S, SA> a) {
+__global__ ECG_SPMM_ATTR void k_spmm(SpArgs<S, SA> a) {
   using C = SpCfg<TPI>;
   constexpr int EPL = C::EPL, RPL = C::RPL, T2 = TPI * TPI;
   constexpr int L = 3 * T2 + TPI;
@@ -579,22 +620,22 @@ __global__ ECG_STREAM void k_spmm(SpArgs<S, SA> a) {
   auto load_rowptr = [&](int64_t step, RowPtr& rp) {
     const int64_t row0 = step * C::WGROWS + wave * C::WROWS + rq;
     for (int q = 0; q < RPL; ++q) {
+      // rows past the end take row n-1's entries; their results are masked
       const int64_t row = row0 + 4 * q;
       const int64_t rc = row < n ? row : n - 1;
-      rp.p0[q] = a.rowptr[rc];
-      const int pe = a.rowptr[rc + 1];
-      rp.p1[q] = row < n ? pe : rp.p0[q];
+      rp.p0[q] = ld_s(a.rowptr + rc);
+      rp.p1[q] = ld_s(a.rowptr + rc + 1);
     }
   };
   auto load_chunk = [&](const RowPtr& rp, int c, Head& h) {
     for (int q = 0; q < RPL; ++q) {
       const int idx = rp.p0[q] + c + (m % kChunk);
-      const bool okm = idx < rp.p1[q];
       const int idc = min(idx, nnz_last);
-      const int64_t col = a.colind[idc];
-      const double vv = static_cast<double>(a.vals[idc]);
-      h.offb[q] = __builtin_bit_cast(double, (int64_t)(okm ? col * TPI : 0));
-      h.valb[q] = okm ? vv : 0.0;
+      const int64_t msk = opaque((int64_t)(idx < rp.p1[q] ? -1 : 0));
+      const double okf = opaque(idx < rp.p1[q] ? 1.0 : 0.0);
+      const int64_t col = ld_s(a.colind + idc);
+      h.offb[q] = __builtin_bit_cast(double, (int64_t)(col * TPI) & msk);
+      h.valb[q] = static_cast<double>(ld_s(a.vals + idc)) * okf;
     }
   };
   auto gather = [&](const Head& h, double (&y)[RPL][EPL]) {
@@ -628,28 +669,26 @@ __global__ ECG_STREAM void k_spmm(SpArgs<S, SA> a) {
     const int64_t row0 = step * C::WGROWS + wave * C::WROWS + rq;
     int64_t rowc[RPL];
     bool ok[RPL];
+    double okf[RPL];
     int len = 0;
     for (int q = 0; q < RPL; ++q) {
       const int64_t row = row0 + 4 * q;
       ok[q] = row < n;
       rowc[q] = ok[q] ? row : n - 1;
+      okf[q] = opaque(ok[q] ? 1.0 : 0.0);
       len = max(len, rp_cur.p1[q] - rp_cur.p0[q]);
     }
-    // operands of the Gram epilogue, independent of the product
+    // operands of the Gram epilogue, independent of the product (rvec is
+    // always given with the Grams)
     double z[RPL][EPL], pz[RPL][EPL], rv[RPL];
     if constexpr (GRAMS) {
       for (int q = 0; q < RPL; ++q) {
-        const double r = a.rvec ? a.rvec[rowc[q]] : 0.0;
-        rv[q] = ok[q] ? r : 0.0;
+        rv[q] = ld_s(a.rvec + rowc[q]) * okf[q];
         for (int e = 0; e < EPL; ++e) {
-          const double zz = ld(a.Z + rowc[q] * TPI + m + 16 * e);
-          z[q][e] = ok[q] ? zz : 0.0;
-          if constexpr (HAS_PREV) {
-            const double pp = ld(a.AZprev + rowc[q] * TPI + m + 16 * e);
-            pz[q][e] = ok[q] ? pp : 0.0;
-          } else {
-            pz[q][e] = 0.0;
-          }
+          z[q][e] = ld(a.Z + rowc[q] * TPI + m + 16 * e) * okf[q];
+          if constexpr (HAS_PREV)
+            pz[q][e] = static_cast<double>(ld_s(a.AZprev + rowc[q] * TPI + m + 16 * e)) * okf[q];
+          else pz[q][e] = 0.0;
         }
       }
     }
@@ -664,12 +703,13 @@ __global__ ECG_STREAM void k_spmm(SpArgs<S, SA> a) {
     }
     for (int q = 0; q < RPL; ++q)
       if (ok[q])
-        for (int e = 0; e < EPL; ++e) a.AZ[rowc[q] * TPI + m + 16 * e] = static_cast<S>(y[q][e]);
+        for (int e = 0; e < EPL; ++e) st_s(a.AZ + rowc[q] * TPI + m + 16 * e, static_cast<S>(y[q][e]));
     if constexpr (GRAMS) {
       for (int q = 0; q < RPL; ++q) {
         for (int e = 0; e < EPL; ++e) {
-          // the stored (rounded) value of AZ enters the Grams
-          y[q][e] = static_cast<double>(static_cast<S>(y[q][e]));
+          // the stored (rounded) value of AZ enters the Grams; rows past
+          // the end contribute nothing
+          y[q][e] = static_cast<double>(static_cast<S>(y[q][e])) * okf[q];
         }
         for (int i = 0; i < EPL; ++i) {
           av[i] = __builtin_fma(z[q][i], rv[q], av[i]);
@@ -737,10 +777,14 @@ __global__ ECG_STREAM void k_xr(XRArgs<S> a) {
     const int64_t row0 = step * WGROWS + wave * WROWS + rq;
     int64_t rowc[RPL];
     bool ok[RPL];
+    double xo[RPL], ro[RPL];
     for (int q = 0; q < RPL; ++q) {
       const int64_t row = row0 + 4 * q;
       ok[q] = row < n;
       rowc[q] = ok[q] ? row : n - 1;
+      // issued with the block loads; only lane m = 0 of a row uses them
+      xo[q] = a.x[rowc[q]];
+      ro[q] = a.r[rowc[q]];
     }
     double dx[RPL], dr[RPL];
     for (int q = 0; q < RPL; ++q) {
@@ -771,9 +815,9 @@ __global__ ECG_STREAM void k_xr(XRArgs<S> a) {
         dx[q] += __shfl_xor(dx[q], off, 16);
         dr[q] += __shfl_xor(dr[q], off, 16);
       }
+      const double rn = ro[q] - dr[q];
       if (m == 0 && ok[q]) {
-        a.x[rowc[q]] += dx[q];
-        const double rn = a.r[rowc[q]] - dr[q];
+        a.x[rowc[q]] = xo[q] + dx[q];
         a.r[rowc[q]] = rn;
         rr += rn * rn;
       }
