@@ -12,6 +12,19 @@ namespace ecg {
 constexpr int kThreads = 256;     // threads per work-group of the block kernels
 constexpr int kMaxS = 16;         // largest s supported by the x/r update
 
+// Blocks of at least ECG_CS_MIN_TPI stored columns (64: at 32 the
+// row-per-lane-group kernels are faster) use the column-split
+// kernels: work-groups of cs_threads(TPI) threads in kCSGroups row groups,
+// each row group writing its own Gram partial.
+#ifndef ECG_CS_MIN_TPI
+#define ECG_CS_MIN_TPI 64
+#endif
+constexpr int kCSGroups = 2;
+constexpr int cs_threads(int tpi) { return tpi == 64 ? 512 : 256; }
+constexpr bool uses_cs(int tpi) { return tpi >= ECG_CS_MIN_TPI; }
+// Gram partials written by a launch of `grid` work-groups.
+constexpr int gram_partials(int tpi, int grid) { return uses_cs(tpi) ? grid * kCSGroups : grid; }
+
 // Deterministic reduction over work-groups: every work-group of a streaming
 // kernel writes its partial vector; k_reduce_groups then sums groups of
 // `group_size` partials in index order and k_final sums the group sums in

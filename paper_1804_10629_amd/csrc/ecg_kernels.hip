@@ -132,6 +132,15 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #ifndef ECG_SP_CHUNK
 #define ECG_SP_CHUNK 8
 #endif
+#ifndef ECG_CS_RPL
+#define ECG_CS_RPL 2           // row quads per lane of the column-split kernels
+#endif
+#ifndef ECG_CS_CHAINS
+#define ECG_CS_CHAINS 4        // accumulation chains per output of the column-split update
+#endif
+#ifndef ECG_CS_WPE
+#define ECG_CS_WPE 2
+#endif
 
 
 template <int TPI>
@@ -756,11 +765,297 @@ __global__ ECG_SPMM_ATTR void k_spmm(SpArgs<S, SA> a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Column-split forms for blocks of 32 and 64 stored columns.  A row group of
+// TPI/16 waves shares its rows; wave w computes the output columns
+// [16 cb, 16 cb + 16), cb = w mod (TPI/16), and the Gram columns of the same
+// block, so a lane holds one output value per row and 16 x TPI Gram
+// accumulators per Gram instead of TPI x TPI.  The waves of a row group load
+// the same full operand rows (the repeats hit the cache).  Every row group
+// writes its own partial: the partial count is the grid times kCSGroups.
+// ---------------------------------------------------------------------------
+
+template <int TPI>
+struct CsCfg {
+  static constexpr int EPL = TPI / 16;                 // column blocks = waves per row group
+  static constexpr int THREADS = cs_threads(TPI);
+  static constexpr int NWAVE = THREADS / 64;
+  static constexpr int RGRP = NWAVE / EPL;             // row groups per work-group (kCSGroups)
+  static constexpr int RPL = ECG_CS_RPL;               // row quads per lane
+  static constexpr int WROWS = 4 * RPL;
+  static constexpr int WGROWS = WROWS * RGRP;
+  static constexpr int T2 = TPI * TPI;
+  static_assert(RGRP == kCSGroups, "row groups per work-group");
+};
+
+// v[cb] for a wave-uniform runtime cb, without indexing a register array
+template <int EPL>
+__device__ __forceinline__ double pick(const double (&v)[EPL], int cb) {
+  double r = v[0];
+  for (int e = 1; e < EPL; ++e) r = (cb == e) ? v[e] : r;
+  return r;
+}
+
+template <int TPI, typename S, int NU, int NG, bool IDENT0, bool WRITE, bool P0X>
+__global__ __launch_bounds__(cs_threads(TPI)) __attribute__((amdgpu_waves_per_eu(ECG_CS_WPE, ECG_CS_WPE)))
+void k_update_gram_cs(UGArgs<S> a) {
+  using C = CsCfg<TPI>;
+  constexpr int EPL = C::EPL, RPL = C::RPL, T2 = C::T2;
+  constexpr int NCOEF = NU - (IDENT0 ? 1 : 0);
+  constexpr int NX = NU;
+  constexpr int NP = NG - (P0X ? 1 : 0);
+  constexpr int NLD = NX + NP;
+  constexpr int LDSN = NCOEF * T2 > 0 ? NCOEF * T2 : 1;
+  __shared__ double lds[LDSN];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = lane & 15, rq = lane >> 4;
+  const int cb = wave % EPL, rg = wave / EPL;
+
+  for (int b = 0; b < NCOEF; ++b) {
+    const double* src = a.C[b + (IDENT0 ? 1 : 0)];
+    for (int idx = tid; idx < T2; idx += blockDim.x) lds[b * T2 + idx] = src[idx];
+  }
+  __syncthreads();
+
+  d4 acc[NG > 0 ? NG : 1][EPL];
+  for (int g = 0; g < (NG > 0 ? NG : 1); ++g)
+    for (int i = 0; i < EPL; ++i) acc[g][i] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const S* src[NLD];
+  for (int b = 0; b < NX; ++b) src[b] = a.X[b];
+  for (int g = 0; g < NP; ++g) src[NX + g] = a.P[g + (P0X ? 1 : 0)];
+
+  const int64_t n = a.n;
+  const Steps sp = my_steps((n + C::WGROWS - 1) / C::WGROWS);
+  for (int64_t step = sp.first; step < sp.end; step += sp.stride) {
+    const int64_t row0 = step * C::WGROWS + rg * C::WROWS + rq;
+    double cur[NLD][RPL][EPL];
+    for (int q = 0; q < RPL; ++q) {
+      const int64_t row = row0 + 4 * q;
+      const int64_t rc = row < n ? row : n - 1;
+      const double okf = opaque(row < n ? 1.0 : 0.0);
+      for (int b = 0; b < NLD; ++b)
+        for (int e = 0; e < EPL; ++e) cur[b][q][e] = ld(src[b] + rc * TPI + m + 16 * e) * okf;
+    }
+    // NCH independent accumulation chains per row (the k-blocks of all
+    // coefficient matrices in turn): one chain would serialise NCOEF * TPI
+    // dependent FMAs per step
+    constexpr int NCH = ECG_CS_CHAINS;
+    double oc[NCH][RPL];
+    for (int h = 0; h < NCH; ++h)
+      for (int q = 0; q < RPL; ++q) oc[h][q] = (h == 0 && IDENT0) ? pick<EPL>(cur[0][q], cb) : 0.0;
+    constexpr int CG = ECG_UG_CGROUP;
+    static_for<NCOEF>([&](auto bc) {
+      constexpr int b = decltype(bc)::value;
+      constexpr int xb = b + (IDENT0 ? 1 : 0);
+      static_for<EPL>([&](auto ec) {
+        constexpr int e2 = decltype(ec)::value;
+        constexpr int h = (b * EPL + e2) % NCH;
+        static_for<16 / CG>([&](auto gc) {
+          constexpr int g0 = CG * decltype(gc)::value;
+          asm volatile("" ::: "memory");
+          double cv[CG];
+          for (int u = 0; u < CG; ++u) cv[u] = lds[b * T2 + (16 * e2 + g0 + u) * TPI + 16 * cb + m];
+          static_for<CG>([&](auto uc) {
+            constexpr int u = decltype(uc)::value;
+            constexpr int nn = g0 + u;
+            for (int q = 0; q < RPL; ++q)
+              oc[h][q] = nn == 0 ? fmac_bcast<nn, true>(oc[h][q], cur[xb][q][e2], cv[u])
+                                 : fmac_bcast<nn, false>(oc[h][q], cur[xb][q][e2], cv[u]);
+          });
+        });
+      });
+    });
+    double o[RPL];
+    for (int q = 0; q < RPL; ++q) {
+      o[q] = oc[0][q];
+      for (int h = 1; h < NCH; ++h) o[q] += oc[h][q];
+    }
+    if constexpr (WRITE) {
+      for (int q = 0; q < RPL; ++q) {
+        const int64_t row = row0 + 4 * q;
+        if (row < n) a.out[row * TPI + 16 * cb + m] = static_cast<S>(o[q]);
+      }
+    }
+    if constexpr (NG > 0) {
+      static_for<NG>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        constexpr int slot = (P0X && g == 0) ? 0 : NX + g - (P0X ? 1 : 0);
+        for (int q = 0; q < RPL; ++q)
+          for (int i = 0; i < EPL; ++i) acc[g][i] = mfma16(cur[slot][q][i], o[q], acc[g][i]);
+      });
+    }
+  }
+  if constexpr (NG > 0) {
+    // this row group's partial: G_g[16 i + 4 v + rq][16 cb + m]
+    double* mine = a.rc.partials + ((size_t)blockIdx.x * C::RGRP + rg) * (NG * T2);
+    for (int g = 0; g < NG; ++g)
+      for (int i = 0; i < EPL; ++i)
+        for (int v = 0; v < 4; ++v) mine[g * T2 + (16 * i + 4 * v + rq) * TPI + 16 * cb + m] = acc[g][i][v];
+  }
+}
+
+template <int TPI, typename S, typename SA, bool GRAMS, bool HAS_PREV>
+__global__ __launch_bounds__(cs_threads(TPI)) __attribute__((amdgpu_waves_per_eu(ECG_CS_WPE, ECG_CS_WPE)))
+void k_spmm_cs(SpArgs<S, SA> a) {
+  using C = CsCfg<TPI>;
+  constexpr int EPL = C::EPL, RPL = C::RPL, T2 = C::T2;
+  constexpr int L = 3 * T2 + TPI;
+  // A Z rows of the current step, shared by the waves of a row group (F Gram)
+  __shared__ double yt[GRAMS ? 2 : 1][GRAMS ? C::RGRP * C::WROWS * TPI : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = lane & 15, rq = lane >> 4;
+  const int cb = wave % EPL, rg = wave / EPL;
+
+  d4 accG[EPL], accF[EPL], accE[EPL];
+  for (int i = 0; i < EPL; ++i) {
+    accG[i] = d4{0.0, 0.0, 0.0, 0.0};
+    accF[i] = d4{0.0, 0.0, 0.0, 0.0};
+    accE[i] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  double av = 0.0;
+  const int64_t n = a.n;
+  const int nnz_last = a.rowptr[n] - 1;
+  const Steps sp = my_steps((n + C::WGROWS - 1) / C::WGROWS);
+
+  // software pipeline as in k_spmm: row pointers two steps ahead, the first
+  // chunk of (column, value) pairs one step ahead of the gather
+  struct RowPtr {
+    int p0[RPL], p1[RPL];
+  };
+  struct Head {
+    double offb[RPL], valb[RPL];
+  };
+  auto load_rowptr = [&](int64_t step, RowPtr& rp) {
+    const int64_t row0 = step * C::WGROWS + rg * C::WROWS + rq;
+    for (int q = 0; q < RPL; ++q) {
+      const int64_t row = row0 + 4 * q;
+      const int64_t rc = row < n ? row : n - 1;
+      rp.p0[q] = ld_s(a.rowptr + rc);
+      rp.p1[q] = ld_s(a.rowptr + rc + 1);
+    }
+  };
+  auto load_chunk = [&](const RowPtr& rp, int c, Head& h) {
+    for (int q = 0; q < RPL; ++q) {
+      const int idx = rp.p0[q] + c + (m % kChunk);
+      const int idc = min(idx, nnz_last);
+      const int64_t msk = opaque((int64_t)(idx < rp.p1[q] ? -1 : 0));
+      const double okm = opaque(idx < rp.p1[q] ? 1.0 : 0.0);
+      const int64_t col = ld_s(a.colind + idc);
+      h.offb[q] = __builtin_bit_cast(double, (int64_t)(col * TPI) & msk);
+      h.valb[q] = static_cast<double>(ld_s(a.vals + idc)) * okm;
+    }
+  };
+  auto gather = [&](const Head& h, double (&y)[RPL]) {
+    static_for<kChunk>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      for (int q = 0; q < RPL; ++q) {
+        const int64_t off = __builtin_bit_cast(int64_t, bcast64<j>(h.offb[q]));
+        const double vj = bcast64<j>(h.valb[q]);
+        y[q] = __builtin_fma(vj, ld(a.Z + off + 16 * cb + m), y[q]);
+      }
+    });
+  };
+
+  RowPtr rp_cur, rp_nxt;
+  Head h_cur;
+  int64_t step = sp.first;
+  if (step < sp.end) {
+    load_rowptr(step, rp_cur);
+    load_chunk(rp_cur, 0, h_cur);
+    if (step + sp.stride < sp.end) load_rowptr(step + sp.stride, rp_nxt);
+  }
+  int buf = 0;
+  for (; step < sp.end; step += sp.stride) {
+    const int64_t s1 = step + sp.stride, s2 = s1 + sp.stride;
+    const bool has1 = s1 < sp.end, has2 = s2 < sp.end;
+    Head h_nxt;
+    RowPtr rp_nn;
+    if (has1) load_chunk(rp_nxt, 0, h_nxt);
+    if (has2) load_rowptr(s2, rp_nn);
+
+    const int64_t row0 = step * C::WGROWS + rg * C::WROWS + rq;
+    int64_t rowc[RPL];
+    double okf[RPL];
+    int len = 0;
+    for (int q = 0; q < RPL; ++q) {
+      const int64_t row = row0 + 4 * q;
+      rowc[q] = row < n ? row : n - 1;
+      okf[q] = opaque(row < n ? 1.0 : 0.0);
+      len = max(len, rp_cur.p1[q] - rp_cur.p0[q]);
+    }
+    double z[RPL][EPL], pz[RPL][EPL], rv[RPL];
+    if constexpr (GRAMS) {
+      for (int q = 0; q < RPL; ++q) {
+        rv[q] = ld_s(a.rvec + rowc[q]) * okf[q];
+        for (int e = 0; e < EPL; ++e) {
+          z[q][e] = ld(a.Z + rowc[q] * TPI + m + 16 * e) * okf[q];
+          if constexpr (HAS_PREV)
+            pz[q][e] = static_cast<double>(ld_s(a.AZprev + rowc[q] * TPI + m + 16 * e)) * okf[q];
+          else
+            pz[q][e] = 0.0;
+        }
+      }
+    }
+    double y[RPL];
+    for (int q = 0; q < RPL; ++q) y[q] = 0.0;
+    gather(h_cur, y);
+    for (int c = kChunk; c < len; c += kChunk) {   // rows longer than one chunk
+      Head h;
+      load_chunk(rp_cur, c, h);
+      gather(h, y);
+    }
+    for (int q = 0; q < RPL; ++q) {
+      const int64_t row = row0 + 4 * q;
+      if (row < n) st_s(a.AZ + row * TPI + 16 * cb + m, static_cast<S>(y[q]));
+    }
+    if constexpr (GRAMS) {
+      double* t = &yt[buf][rg * C::WROWS * TPI];
+      for (int q = 0; q < RPL; ++q) {
+        // the stored (rounded) value of A Z enters the Grams
+        y[q] = static_cast<double>(static_cast<S>(y[q])) * okf[q];
+        t[(rq + 4 * q) * TPI + 16 * cb + m] = y[q];
+      }
+      __syncthreads();
+      for (int q = 0; q < RPL; ++q) {
+        av = __builtin_fma(pick<EPL>(z[q], cb), rv[q], av);
+        for (int i = 0; i < EPL; ++i) {
+          const double yi = t[(rq + 4 * q) * TPI + 16 * i + m];
+          accG[i] = mfma16(z[q][i], y[q], accG[i]);
+          accF[i] = mfma16(yi, y[q], accF[i]);
+          if constexpr (HAS_PREV) accE[i] = mfma16(pz[q][i], y[q], accE[i]);
+        }
+      }
+      buf ^= 1;   // the next step writes the other tile: one barrier per step
+    }
+    if (has1) {
+      h_cur = h_nxt;
+      rp_cur = rp_nxt;
+    }
+    if (has2) rp_nxt = rp_nn;
+  }
+  if constexpr (GRAMS) {
+    av += __shfl_xor(av, 16, 64);
+    av += __shfl_xor(av, 32, 64);
+    double* mine = a.rc.partials + ((size_t)blockIdx.x * C::RGRP + rg) * L;
+    for (int i = 0; i < EPL; ++i)
+      for (int v = 0; v < 4; ++v) {
+        const int idx = (16 * i + 4 * v + rq) * TPI + 16 * cb + m;
+        mine[idx] = accG[i][v];
+        mine[T2 + idx] = accF[i][v];
+        mine[2 * T2 + idx] = accE[i][v];
+      }
+    if (rq == 0) mine[3 * T2 + 16 * cb + m] = av;
+  }
+}
+
 // x += sum_i U_i beta_i ; r -= sum_i AU_i beta_i ; ||r||^2.  Blocks are
 // taken four at a time so that eight loads per row are in flight.
 template <int TPI, typename S>
 __global__ ECG_STREAM void k_xr(XRArgs<S> a) {
-  constexpr int EPL = TPI / 16, RPL = 4, WROWS = 4 * RPL, NWAVE = kThreads / 64;
+  constexpr int EPL = TPI / 16, RPL = TPI == 16 ? 4 : (TPI == 32 ? 2 : 1);
+  constexpr int WROWS = 4 * RPL, NWAVE = kThreads / 64;
   constexpr int WGROWS = WROWS * NWAVE, NB4 = 4;
   __shared__ double bl[kMaxS * TPI];
   __shared__ double red[8];
@@ -1032,8 +1327,12 @@ hipError_t launch_update_gram(int nu, int ng, bool ident0, bool write_out, int t
 #define ECG_UG(NU, NG, ID, WR, TL, P0X)                                                   \
   if (nu == NU && ng == NG && ident0 == ID && write_out == WR && tail == TL &&             \
       (a.P[0] == a.X[0]) == P0X) {                                                         \
-    hipLaunchKernelGGL((k_update_gram<TPI, S, NU, NG, ID, WR, TL, P0X>), dim3(grid),       \
-                       dim3(kThreads), 0, st, a);                                          \
+    if constexpr (uses_cs(TPI))                                                            \
+      hipLaunchKernelGGL((k_update_gram_cs<TPI, S, NU, NG, ID, WR, P0X>), dim3(grid),      \
+                         dim3(cs_threads(TPI)), 0, st, a);                                 \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_update_gram<TPI, S, NU, NG, ID, WR, TL, P0X>), dim3(grid),     \
+                         dim3(kThreads), 0, st, a);                                        \
     return hipGetLastError();                                                              \
   }
   // first CGS pass of blocks m = 2 and m >= 3 (fused with the second Gram)
@@ -1059,6 +1358,17 @@ hipError_t launch_update_gram(int nu, int ng, bool ident0, bool write_out, int t
 template <int TPI, typename S, typename SA>
 hipError_t launch_spmm(bool grams, bool has_prev, int tail, const SpArgs<S, SA>& a, int grid,
                        hipStream_t st) {
+  if constexpr (uses_cs(TPI)) {
+    const dim3 blk(cs_threads(TPI));
+    if (grams && tail != TAIL_SPMM) return hipErrorInvalidValue;
+    if (!grams)
+      hipLaunchKernelGGL((k_spmm_cs<TPI, S, SA, false, false>), dim3(grid), blk, 0, st, a);
+    else if (has_prev)
+      hipLaunchKernelGGL((k_spmm_cs<TPI, S, SA, true, true>), dim3(grid), blk, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_spmm_cs<TPI, S, SA, true, false>), dim3(grid), blk, 0, st, a);
+    return hipGetLastError();
+  }
   if (!grams) {
     hipLaunchKernelGGL((k_spmm<TPI, S, SA, false, false, TAIL_NONE>), dim3(grid), dim3(kThreads),
                        0, st, a);

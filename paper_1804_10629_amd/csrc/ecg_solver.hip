@@ -393,13 +393,14 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
     c->grid = std::max(1, g);
   }
   const int max_grid = std::max(c->grid, 1024);
-  const int ngroups = (max_grid + c->group_size - 1) / c->group_size;
+  const int max_partials = max_grid * kCSGroups;   // column-split kernels: per row group
+  const int ngroups = (max_partials + c->group_size - 1) / c->group_size;
   const size_t L = 3 * (size_t)T2 + tpi;
 
   // ---- workspace size check ----
   const size_t esz = c->sbytes;
   const double fixed = blk * esz + (double)nnz * (4 + 8 + (o.precision ? 4 : 0)) +
-                       4.0 * (n + 1) + 4.0 * n + 3.0 * 8 * n + (double)max_grid * L * 8 +
+                       4.0 * (n + 1) + 4.0 * n + 3.0 * 8 * n + (double)max_partials * L * 8 +
                        (double)ngroups * L * 8;
   const double per_slot = 2.0 * blk * esz + 8.0 * (3.0 * T2 + tpi);
   size_t freeb = 0, totalb = 0;
@@ -464,7 +465,7 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
     ALLOC(c->dtab, double, (size_t)c->nslot * T2);
   }
   ALLOC(c->status, DevStatus, 1);
-  ALLOC(c->partials, double, (size_t)max_grid * L);
+  ALLOC(c->partials, double, (size_t)max_partials * L);
   ALLOC(c->groups, double, (size_t)ngroups * L);
 #undef ALLOC
   if (hipHostMalloc((void**)&c->h_status, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess)
@@ -590,7 +591,7 @@ struct Engine {
         ta.coef_out[k] = c->ctab + (size_t)(p0 + k) * T2;
       }
       ta.rinv_right = rinv(newest);
-      if ((rc = reduce(c->grid, len * T2, TAIL_GRAM, len, ta))) return rc;
+      if ((rc = reduce(gram_partials(TPI, c->grid), len * T2, TAIL_GRAM, len, ta))) return rc;
     }
     // (b) first update: Z' = A U_{m-1} C0 + U_{m-1} C1 + U_{m-2} C2 + sum_p U_p C_p
     {
@@ -636,7 +637,7 @@ struct Engine {
         ta.coef_out[k] = c->dtab + (size_t)(p0 + k) * T2;
       }
       ta.rinv_right = nullptr;
-      if ((rc = reduce(c->grid, len * T2, TAIL_GRAM, len, ta))) return rc;
+      if ((rc = reduce(gram_partials(TPI, c->grid), len * T2, TAIL_GRAM, len, ta))) return rc;
     }
     // (d) second update: U_m = Z' + sum_p U_p D_p (in place after the first chunk)
     for (int p0 = 0; p0 <= m - 2; p0 += CH) {
@@ -671,7 +672,7 @@ struct Engine {
     if (rc) return rc;
     TailArgs ta = tail0(m);
     ta.coef_out[0] = c->pre_rinv;
-    if ((rc = reduce(c->grid, T2, TAIL_PRE, 1, ta))) return rc;
+    if ((rc = reduce(gram_partials(TPI, c->grid), T2, TAIL_PRE, 1, ta))) return rc;
     UGArgs<S> u{};
     u.X[0] = U(slot);
     u.C[0] = c->pre_rinv;
@@ -715,7 +716,7 @@ struct Engine {
       c->tstart(tm, ECG_K_CGS_GRAM, (2.0 * np + 1.0) * bb, 2.0 * nt2 * (2 * np + 1 + np));
       HIP_TRY((launch_update_gram<TPI, S>(np + 1, np, false, true, TAIL_CGS, ka, c->grid, c->st)));
       c->tstop(tm);
-      int rc = reduce(c->grid, np * TPI * TPI, TAIL_CGS, np, ka.tail);
+      int rc = reduce(gram_partials(TPI, c->grid), np * TPI * TPI, TAIL_CGS, np, ka.tail);
       if (rc) return rc;
 
       UGArgs<S> kb{};
@@ -757,7 +758,7 @@ struct Engine {
               2.0 * c->nnz * c->t + 2.0 * nt2 * (m >= 2 ? 3 : 2) + 2.0 * c->n * c->t);
     HIP_TRY((launch_spmm<TPI, S, SA>(true, m >= 2, TAIL_SPMM, sa, c->grid, c->st)));
     c->tstop(tm);
-    return reduce(c->grid, 3 * TPI * TPI + TPI, TAIL_SPMM, 0, sa.tail);
+    return reduce(gram_partials(TPI, c->grid), 3 * TPI * TPI + TPI, TAIL_SPMM, 0, sa.tail);
   }
 
   int xr(const int* slots, int nb) {
