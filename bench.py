@@ -15,8 +15,10 @@ oracle timed on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -76,11 +78,46 @@ def kernel_table(stats):
     return out
 
 
-def cpu_baseline(p, gpu_iters, budget_iters=1):
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1804_10629_amd", "csrc", "ecg_kernels.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kclass, workload):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    --pmc summary (FETCH_SIZE and WRITE_SIZE, scaled against a plain copy),
+    or None when no summary matches this workload and kernel source."""
+    src = kernel_source_hash()
+    if not os.path.isdir(PROFILES):
+        return None
+    for name in sorted(os.listdir(PROFILES)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(PROFILES, name)) as f:
+            for line in f:
+                m = re.match(r"^traffic_json: (\{.*\})\s*$", line)
+                if not m:
+                    continue
+                d = json.loads(m.group(1))
+                if (d.get("kclass") == kclass and d.get("workload") == workload
+                        and d.get("kernel_source_sha256_16") == src):
+                    return d
+    return None
+
+
+def cpu_baseline(p, gpu_iters, budget_iters=5):
     import oracle as O
     A = p.scipy()
     dom = O.partition_grid(p.shape, p.parts)
-    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.cpu_count() or 1))
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     r = O.sstep_srecg(A, dom, p.t, p.s, p.b, tol=p.tol, maxit=budget_iters)
     dt = time.perf_counter() - t0
@@ -156,13 +193,20 @@ def main():
     ktab = kernel_table(stats)
     solver.close()
 
-    # dominant kernel by device time
+    # dominant kernel class by device time: algorithmic bytes per launch over
+    # its mean launch time (HIP events on the solver's stream)
     dom_name = max(ktab, key=lambda k: ktab[k]["ms_total"])
     dk = ktab[dom_name]
     achieved = dk["gb_per_launch"] / (dk["us_per_launch"] * 1e-6)
-    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1),
-                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": None}
+    tr = measured_traffic(dom_name, p.name)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": tr["hbm_gb_per_launch"] if tr else None,
+                "kernel": dom_name, "algorithmic_gb_per_launch": dk["gb_per_launch"],
+                "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                "traffic_vs_algorithmic": (round(tr["hbm_gb_per_launch"] / dk["gb_per_launch"], 3)
+                                           if tr else None),
+                "traffic_source": tr["file"] if tr else None}
 
     mixed = None
     if not args.no_mixed:
