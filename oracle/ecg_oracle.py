@@ -313,13 +313,17 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
                 orth="acholqr", aimage="stored", basis_dtype=np.float64,
                 inner_tol=0.0, max_restarts=20, q_cap_blocks=0,
                 record=False, stop_after_blocks: Optional[int] = None) -> SolveResult:
-    """s-step SRE-CG (variant='srecg') / s-step SRE-CG2 ('srecg2').
+    """s-step SRE-CG (variant='srecg') / s-step SRE-CG2 ('srecg2') / s-step
+    MSDO-CG ('msdo', Section 3.2, algorithm "s-step MSDO-CG").
 
     One s-step iteration builds blocks W_j .. W_{j+s-1} (t columns each),
     where the first block after a (re)start is T(r) and every later block
     starts from A W_{j-1}; each is A-orthonormalized against W_{j-2}, W_{j-1}
     (SRE-CG) or against all blocks since the (re)start (SRE-CG2) with CGS2,
     then against itself (A-CholQR, or Pre-CholQR with orth='precholqr').
+    s-step MSDO-CG is SRE-CG2 with the first block of every iteration split
+    from the current residual, T(r_{k-1}): the basis spans the modified
+    enlarged Krylov subspace {T(r_i), A T(r_i), .., A^{s-1} T(r_i)}.
     With V = [W_j .. W_{j+s-1}]: alpha = V^t r_{k-1}, x_k = x_{k-1} + V alpha,
     r_k = r_{k-1} - (AV) alpha, rho = ||r_k||_2; stop when rho <= tol*rho_0.
 
@@ -339,11 +343,14 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
         matrix values used for the basis in float32, keeps every Gram,
         Cholesky factor, alpha, x and r in float64, and restarts (an
         iterative-refinement step) whenever rho <= inner_tol * rho_restart;
-      * SRE-CG2 keeps all blocks since the last restart; when q_cap_blocks
-        > 0 and another s blocks would exceed it, the solve restarts from x.
+      * SRE-CG2 and MSDO-CG keep all blocks since the last restart; when
+        q_cap_blocks > 0 and another s blocks would exceed it, the solve
+        restarts from x.
     """
     if s < 1 or t < 1:
         raise ValueError("s and t must be >= 1")
+    if variant not in ("srecg", "srecg2", "msdo"):
+        raise ValueError("variant must be 'srecg', 'srecg2' or 'msdo'")
     dtype = np.dtype(basis_dtype).type
     Ab = A if dtype == np.float64 else csr(A.indptr, A.indices,
                                            A.data.astype(np.float32).astype(np.float64),
@@ -375,7 +382,7 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
     while True:
         thr = max(inner_tol * rho_restart, thr_final)
         while rho > thr and k < maxit:
-            if (variant == "srecg2" and q_cap_blocks and not fresh_start
+            if (variant != "srecg" and q_cap_blocks and not fresh_start
                     and len(blocks) + s > q_cap_blocks):
                 r = b - A @ x
                 rho = float(np.linalg.norm(r))
@@ -388,7 +395,7 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
             V, AV = [], []
             try:
                 for i in range(s):
-                    if fresh_start:
+                    if fresh_start or (variant == "msdo" and i == 0):
                         Z = _store(split_T(r, dom, t), dtype)
                         fresh_start = False
                     elif aimage == "stored":

@@ -90,3 +90,20 @@ def monotone_energy_violation(res, A, xstar) -> float:
             worst = max(worst, (E - prev) / prev)
         prev = E
     return worst
+
+
+MSDO_SVALS = [1, 2, 3, 4, 5, 6, 7, 8, 10]
+
+
+def read_msdo_table():
+    """Rows of tests/golden/poisson2d_msdo_iterations.txt as
+    {t: (msdo_cg, [s-step counts for MSDO_SVALS])}."""
+    out = {}
+    with open(os.path.join(GOLDEN, "poisson2d_msdo_iterations.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            v = [int(x) for x in line.split()]
+            out[v[0]] = (v[1], v[2:])
+    return out
