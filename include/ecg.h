@@ -9,7 +9,8 @@
  * graph of A by the operator T (Section 2); every s-step iteration builds
  * s*t A-orthonormal basis vectors V of the enlarged Krylov subspace and
  * updates alpha = V^t r, x += V alpha, r -= A V alpha (eqs (1)-(3) and the
- * algorithms "s-step SRE-CG" and "s-step SRE-CG2" of Section 3.1).
+ * algorithms "s-step SRE-CG" and "s-step SRE-CG2" of Section 3.1, "s-step
+ * MSDO-CG" of Section 3.2).
  *
  * Conventions
  *   - Every function returning int returns an ecg status: 0 (ECG_OK),
@@ -53,8 +54,11 @@ extern "C" {
 /* ---- options ----------------------------------------------------------- */
 enum ecg_variant   { ECG_SRECG = 0,   /* s-step SRE-CG: each block against the
                                          previous two (Section 3.1) */
-                     ECG_SRECG2 = 1   /* s-step SRE-CG2: against every block
-                                         since the last (re)start */ };
+                     ECG_SRECG2 = 1,  /* s-step SRE-CG2: against every block
+                                         since the last (re)start */
+                     ECG_MSDO = 2     /* s-step MSDO-CG (Section 3.2): as
+                                         SRE-CG2, but the first block of every
+                                         iteration is T(r_{k-1}) */ };
 enum ecg_orth      { ECG_ACHOLQR = 0, ECG_PRECHOLQR = 1 };
 enum ecg_precision { ECG_FP64 = 0,    /* everything in binary64 */
                      ECG_MIXED = 1    /* binary32 basis blocks and matrix values
@@ -74,10 +78,11 @@ typedef struct ecg_opts {
                              at the last restart (default 1e-5; ignored in
                              ECG_FP64) */
   int32_t max_restarts;   /* bound on residual replacements (default 20) */
-  int32_t q_cap_blocks;   /* ECG_SRECG2: blocks kept since the last restart; when
-                             another s would exceed it the solve restarts from
-                             x.  0 = as many as ws_cap_bytes allows, at most
-                             2048; otherwise at least s (default 0) */
+  int32_t q_cap_blocks;   /* ECG_SRECG2, ECG_MSDO: blocks kept since the last
+                             restart; when another s would exceed it the
+                             solve restarts from x.  0 = as many as
+                             ws_cap_bytes allows, at most 2048; otherwise at
+                             least s (default 0) */
   int64_t ws_cap_bytes;   /* device workspace cap; 0 = 90% of free memory */
   void*   hip_stream;     /* hipStream_t to run on; NULL = null stream */
   int32_t collect_stats;  /* 1: time every kernel with HIP events (ecg_last_stats) */
@@ -152,12 +157,13 @@ int ecg_partition_grid(int64_t nx, int64_t ny, int64_t nz, int32_t px, int32_t p
  * t domains partition[i] in [0, t) and s blocks per iteration.
  * Copies everything to device memory and allocates the workspace: (s+2)
  * pairs of n x t blocks (basis W and its A-image) for ECG_SRECG, one pair
- * per kept block (q_cap_blocks) for ECG_SRECG2, plus scratch.
+ * per kept block (q_cap_blocks; allocated when first needed) for ECG_SRECG2
+ * and ECG_MSDO, plus scratch.
  * Errors: ECG_EINVAL (out == NULL; n <= 0; t < 1; t > 64; t > n; s < 1;
  * rowptr not starting at 0 or decreasing; nnz >= 2^31; a column index out
  * of [0, n); a partition value out of [0, t); an empty domain; a
- * non-finite value; nonzero reserved fields; ECG_SRECG2 with q_cap_blocks
- * in [1, s)), ECG_ENOMEM (the workspace
+ * non-finite value; nonzero reserved fields; ECG_SRECG2 or ECG_MSDO with
+ * q_cap_blocks in [1, s)), ECG_ENOMEM (the workspace
  * does not fit ws_cap_bytes or device memory), ECG_EDEVICE.  Symmetry and
  * definiteness are not checked here; an indefinite matrix is reported by
  * ecg_solve as ECG_BREAKDOWN.  On error *out is NULL.

@@ -30,7 +30,7 @@ LIB_PATH = os.environ.get("ECG_LIBRARY") or os.path.join(_HERE, "libecg.so")
 
 OK, MAXIT, BREAKDOWN, STAGNATED = 0, 1, 2, 3
 EINVAL, ENOMEM, EDEVICE, ENOTSUP = -1, -2, -3, -4
-SRECG, SRECG2 = 0, 1
+SRECG, SRECG2, MSDO = 0, 1, 2
 ACHOLQR, PRECHOLQR = 0, 1
 FP64, MIXED = 0, 1
 KCLASSES = ["resid", "tsplit", "cgs_gram", "cgs_update", "spmm", "xr_update", "gram",

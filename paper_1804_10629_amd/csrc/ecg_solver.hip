@@ -325,14 +325,15 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   if (t < 1 || t > 64) return fail(ECG_EINVAL, "t must be in [1, 64]");
   if (t > n) return fail(ECG_EINVAL, "t must not exceed n");
   if (s < 1 || s > kMaxS) return fail(ECG_EINVAL, "s must be in [1, 16]");
-  if (o.variant != ECG_SRECG && o.variant != ECG_SRECG2) return fail(ECG_EINVAL, "bad variant");
+  if (o.variant != ECG_SRECG && o.variant != ECG_SRECG2 && o.variant != ECG_MSDO)
+    return fail(ECG_EINVAL, "bad variant");
   if (o.orth != ECG_ACHOLQR && o.orth != ECG_PRECHOLQR) return fail(ECG_EINVAL, "bad orth");
   if (o.precision != ECG_FP64 && o.precision != ECG_MIXED) return fail(ECG_EINVAL, "bad precision");
   if (o.device_ptrs != 0 && o.device_ptrs != 1) return fail(ECG_EINVAL, "bad device_ptrs");
   if (!(o.inner_tol >= 0.0 && o.inner_tol < 1.0)) return fail(ECG_EINVAL, "inner_tol must be in [0, 1)");
   if (o.max_restarts < 0 || o.q_cap_blocks < 0 || o.ws_cap_bytes < 0 || o.grid < 0)
     return fail(ECG_EINVAL, "negative option");
-  if (o.variant == ECG_SRECG2 && o.q_cap_blocks > 0 && o.q_cap_blocks < s)
+  if (o.variant != ECG_SRECG && o.q_cap_blocks > 0 && o.q_cap_blocks < s)
     return fail(ECG_EINVAL, "q_cap_blocks must be 0 or at least s");
   const bool dev = o.device_ptrs == 1;
   if (dev) {
@@ -406,7 +407,7 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   size_t freeb = 0, totalb = 0;
   HIP_TRY(hipMemGetInfo(&freeb, &totalb));
   double cap = o.ws_cap_bytes > 0 ? (double)o.ws_cap_bytes : 0.9 * (double)freeb;
-  if (o.variant == ECG_SRECG2) {
+  if (o.variant != ECG_SRECG) {
     // every block since the last restart is kept: one slot per block, at
     // least the s blocks of one iteration
     int64_t fit = (int64_t)((cap - fixed) / per_slot);
@@ -450,7 +451,7 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   c->U.assign(c->nslot, nullptr);
   c->AU.assign(c->nslot, nullptr);
   {
-    const int first = o.variant == ECG_SRECG2 ? std::min(c->nslot, s + 2) : c->nslot;
+    const int first = o.variant != ECG_SRECG ? std::min(c->nslot, s + 2) : c->nslot;
     if ((rc = grow_slots(c, first))) return cleanup(rc);
   }
   if (o.precision == ECG_MIXED) ALLOC(*(float**)&c->Zp, float, blk);
@@ -460,7 +461,7 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   ALLOC(c->cnext, double, 3 * (size_t)T2);
   ALLOC(c->dcoef, double, 2 * (size_t)T2);
   ALLOC(c->pre_rinv, double, (size_t)T2);
-  if (o.variant == ECG_SRECG2) {
+  if (o.variant != ECG_SRECG) {
     ALLOC(c->ctab, double, (size_t)c->nslot * T2);
     ALLOC(c->dtab, double, (size_t)c->nslot * T2);
   }
@@ -621,11 +622,23 @@ struct Engine {
       if ((rc = ug(ECG_K_UPDATE, 1 + len, 0, true, true, u, (2.0 + len) * bb, 2.0 * nt2 * len)))
         return rc;
     }
-    // (c) second-pass Grams H2'_p = (A U_p)^t Z' for every earlier block
+    // (c), (d) second pass against every earlier block, into the slot
+    if ((rc = pass_gram(m, (const S*)c->Zp, c->dtab))) return rc;
+    return pass_update(m, (const S*)c->Zp, c->dtab, U(slot));
+  }
+
+  // One CGS pass, first half: coefficients tab[p] = -R_p^{-1} R_p^{-t}
+  // (A U_p)^t X for every block p since the restart (slots 0 .. m-2).
+  int pass_gram(int m, const S* X, double* tab) {
+    constexpr int T2 = TPI * TPI;
+    constexpr int CH = TPI == 64 ? 2 : 3;
+    const double bb = c->blk_bytes();
+    const double nt2 = (double)c->n * c->t * c->t;
+    int rc;
     for (int p0 = 0; p0 <= m - 2; p0 += CH) {
       const int len = std::min(CH, m - 1 - p0);
       UGArgs<S> g{};
-      g.X[0] = (const S*)c->Zp;
+      g.X[0] = X;
       for (int k = 0; k < len; ++k) g.P[k] = AU(p0 + k);
       g.n = c->n;
       g.rc = c->rc();
@@ -634,27 +647,53 @@ struct Engine {
       TailArgs ta = tail0(m);
       for (int k = 0; k < len; ++k) {
         ta.rinv_g[k] = rinv(p0 + k);
-        ta.coef_out[k] = c->dtab + (size_t)(p0 + k) * T2;
+        ta.coef_out[k] = tab + (size_t)(p0 + k) * T2;
       }
       ta.rinv_right = nullptr;
       if ((rc = reduce(gram_partials(TPI, c->grid), len * T2, TAIL_GRAM, len, ta))) return rc;
     }
-    // (d) second update: U_m = Z' + sum_p U_p D_p (in place after the first chunk)
+    return ECG_OK;
+  }
+
+  // Second half: out = X + sum_p U_p tab[p] (in place after the first chunk;
+  // out may be X).
+  int pass_update(int m, const S* X, const double* tab, S* out) {
+    constexpr int T2 = TPI * TPI;
+    constexpr int CH = TPI == 64 ? 2 : 3;
+    const double bb = c->blk_bytes();
+    const double nt2 = (double)c->n * c->t * c->t;
+    int rc;
     for (int p0 = 0; p0 <= m - 2; p0 += CH) {
       const int len = std::min(CH, m - 1 - p0);
       UGArgs<S> u{};
-      u.X[0] = p0 == 0 ? (const S*)c->Zp : U(slot);
+      u.X[0] = p0 == 0 ? X : out;
       for (int k = 0; k < len; ++k) {
         u.X[1 + k] = U(p0 + k);
-        u.C[1 + k] = c->dtab + (size_t)(p0 + k) * T2;
+        u.C[1 + k] = tab + (size_t)(p0 + k) * T2;
       }
-      u.out = U(slot);
+      u.out = out;
       u.n = c->n;
       u.rc = c->rc();
       if ((rc = ug(ECG_K_UPDATE, 1 + len, 0, true, true, u, (2.0 + len) * bb, 2.0 * nt2 * len)))
         return rc;
     }
     return ECG_OK;
+  }
+
+  // s-step MSDO-CG (Section 3.2): the first block of an iteration after the
+  // first is T(r_{k-1}), A-orthonormalised against every block since the
+  // restart by two full CGS passes.
+  int msdo_first(int m, int slot) {
+    const double bb = c->blk_bytes();
+    Timed tm;
+    c->tstart(tm, ECG_K_TSPLIT, bb + 12.0 * c->n, 0.0);
+    HIP_TRY((launch_tsplit<TPI, S>(c->r, c->dom, (S*)c->Zp, c->n, c->grid, c->st)));
+    c->tstop(tm);
+    int rc;
+    if ((rc = pass_gram(m, (const S*)c->Zp, c->ctab))) return rc;
+    if ((rc = pass_update(m, (const S*)c->Zp, c->ctab, (S*)c->Zp))) return rc;
+    if ((rc = pass_gram(m, (const S*)c->Zp, c->dtab))) return rc;
+    return pass_update(m, (const S*)c->Zp, c->dtab, U(slot));
   }
 
   // Pre-CholQR: Euclidean CholQR of the block before A-CholQR,
@@ -683,11 +722,15 @@ struct Engine {
   }
 
   // Build block m (1-based since the last restart) into `slot`; p1, p2 are
-  // the slots of blocks m-1 and m-2.
-  int block(int m, int slot, int p1, int p2) {
+  // the slots of blocks m-1 and m-2; `first`: the first block of an s-step
+  // iteration.
+  int block(int m, int slot, int p1, int p2, bool first) {
     const double bb = c->blk_bytes();
     const double nt2 = (double)c->n * c->t * c->t;
-    if (c->o.variant == ECG_SRECG2 && m >= 4) {
+    if (c->o.variant == ECG_MSDO && first && m >= 2) {
+      int rc = msdo_first(m, slot);
+      if (rc) return rc;
+    } else if (c->o.variant != ECG_SRECG && m >= 4) {
       int rc = cgs_all(m, slot);
       if (rc) return rc;
     } else if (m == 1) {
@@ -818,7 +861,7 @@ struct Engine {
     int k = 0, restarts = 0, m = 0, nblocks = 0;
     int status = ECG_OK;
     int ns = c->nslot;
-    const bool cg2 = c->o.variant == ECG_SRECG2;
+    const bool cg2 = c->o.variant != ECG_SRECG;   // every block since the restart is kept
     int slot_of[3] = {-1, -1, -1};   // slots of blocks m, m-1, m-2
     bool have_basis = false;
     while (true) {
@@ -850,7 +893,7 @@ struct Engine {
           slot_of[2] = slot_of[1];
           slot_of[1] = slot_of[0];
           slot_of[0] = slot;
-          if ((rc = block(m, slot, slot_of[1], slot_of[2]))) return rc;
+          if ((rc = block(m, slot, slot_of[1], slot_of[2], i == 0))) return rc;
           slots[i] = slot;
           ++nblocks;
         }

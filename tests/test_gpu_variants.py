@@ -1,6 +1,7 @@
 """GPU parity of the s-step SRE-CG2 variant (every block A-orthonormalised
-against all blocks since the last restart) and of Pre-CholQR (a Euclidean
-CholQR before the A-CholQR), both from the algorithms of Section 3.1,
+against all blocks since the last restart), of Pre-CholQR (a Euclidean
+CholQR before the A-CholQR), both from the algorithms of Section 3.1, and
+of s-step MSDO-CG (Section 3.2),
 through the C ABI against the FP64 oracle.  Same bar as test_gpu_solve.py:
 first iterates and basis to 1e-10, full solves with the iteration count
 within +-2 and x within 1e-6 (ensemble criterion on rounding-sensitive
@@ -183,4 +184,67 @@ def test_srecg2_stats_classes(E, poisson):
     st = sol.stats()
     assert st["gram"]["launches"] > 0 and st["update"]["launches"] > 0
     assert st["spmm"]["launches"] == info.blocks
+    sol.close()
+
+
+# ---------------------------------------------------------------------------
+# s-step MSDO-CG (Section 3.2)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("s", [1, 2, 3])
+def test_msdo_first_iterations_and_basis(E, poisson, s):
+    # s = 1: every block is T(r_{k-1}); s = 2, 3: first blocks from T(r)
+    # followed by SRE-CG2 blocks (one to three chunks of earlier blocks)
+    p, A, dom = poisson
+    ref = O.sstep_srecg(A, dom, 8, s, p.b, tol=1e-8, maxit=5, variant="msdo", record=True)
+    sol = E.Solver(p.rowptr, p.colind, p.vals, dom, 8, s, variant=E.MSDO)
+    for kmax in (1, 2, 3, 5):
+        x, info = sol.solve(p.b, tol=1e-8, maxit=kmax)
+        assert info.status == E.MAXIT and info.iters == kmax
+        assert _rel(x.cpu().numpy(), ref.extra["xs"][kmax]) <= 1e-10, kmax
+        V, AV = (a.cpu().numpy() for a in sol.basis())
+        Vr, AVr = ref.extra["V"][kmax - 1]
+        assert np.abs(V - Vr).max() <= 1e-10 * np.abs(Vr).max(), kmax
+        assert np.abs(AV - AVr).max() <= 1e-10 * np.abs(AVr).max(), kmax
+    sol.close()
+
+
+@pytest.mark.parametrize("m,t,s,parts,orth", [
+    (100, 8, 2, (2, 4, 1), "acholqr"), (100, 8, 2, (2, 4, 1), "precholqr"),
+    (41, 20, 2, (5, 4, 1), "acholqr"), (64, 64, 1, (8, 8, 1), "acholqr")])
+def test_msdo_full_solve_parity(E, m, t, s, parts, orth):
+    p = P.poisson2d(m, t=t, parts=parts, seed=m + 1)
+    A = p.scipy()
+    dom = O.partition_grid(p.shape, parts)
+    ref = O.sstep_srecg(A, dom, t, s, p.b, tol=1e-8, variant="msdo", orth=orth)
+    sol = E.Solver(p.rowptr, p.colind, p.vals, dom, t, s, variant=E.MSDO,
+                   orth=E.PRECHOLQR if orth == "precholqr" else E.ACHOLQR)
+    x, info = sol.solve(p.b, tol=1e-8, maxit=2000)
+    assert info.status == E.OK and info.true_relres <= 1e-8
+    assert abs(info.iters - ref.iters) <= 2, (info.iters, ref.iters)
+    assert _rel(x.cpu().numpy(), ref.x) <= 1e-6
+    sol.close()
+
+
+def test_msdo_block_cap_restarts(E, poisson):
+    p, A, dom = poisson
+    ref = O.sstep_srecg(A, dom, 8, 2, p.b, tol=1e-8, maxit=30, variant="msdo", q_cap_blocks=5,
+                        max_restarts=0)
+    sol = E.Solver(p.rowptr, p.colind, p.vals, dom, 8, 2, variant=E.MSDO, q_cap_blocks=5,
+                   max_restarts=0)
+    x, info = sol.solve(p.b, tol=1e-8, maxit=30)
+    assert info.iters == ref.iters and info.restarts == ref.restarts >= 1
+    assert len(info.hist) == len(ref.hist)
+    np.testing.assert_allclose(info.hist, ref.hist, rtol=1e-8)
+    assert _rel(x.cpu().numpy(), ref.x) <= 1e-9
+    sol.close()
+
+
+def test_msdo_mixed_precision(E, poisson):
+    p, A, dom = poisson
+    sol = E.Solver(p.rowptr, p.colind, p.vals, dom, 8, 2, variant=E.MSDO, precision=E.MIXED)
+    x, info = sol.solve(p.b, tol=1e-8, maxit=1000)
+    x = x.cpu().numpy()
+    assert info.status == E.OK and info.restarts >= 1
+    assert np.linalg.norm(p.b - A @ x) / np.linalg.norm(p.b) <= 1e-8
     sol.close()
