@@ -126,6 +126,12 @@ __device__ __forceinline__ void st_s(T* p, T v) {
   else *p = v;
 }
 
+#ifndef ECG_F32_RPL_MUL
+#define ECG_F32_RPL_MUL 2      // row-quad multiplier of the update kernels for binary32 blocks
+#endif
+#ifndef ECG_F32_SP_RPL_MUL
+#define ECG_F32_SP_RPL_MUL 1   // the same for the product kernel
+#endif
 #ifndef ECG_UG_CGROUP
 #define ECG_UG_CGROUP 4        // coefficient rows read from LDS per group (divides 16)
 #endif
@@ -143,10 +149,12 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #endif
 
 
-template <int TPI>
+template <int TPI, typename S = double>
 struct Cfg {
   static constexpr int EPL = TPI / 16;                              // columns per lane
-  static constexpr int RPL = TPI == 16 ? ECG_UG_RPL16 : (TPI == 32 ? ECG_UG_RPL32 : 1);
+  // binary32 operands take half the registers: more row quads in flight
+  static constexpr int RPL = (TPI == 16 ? ECG_UG_RPL16 : (TPI == 32 ? ECG_UG_RPL32 : 1)) *
+                             (sizeof(S) == 4 ? ECG_F32_RPL_MUL : 1);
   static constexpr int WROWS = 4 * RPL;                             // rows per wave step
   static constexpr int NWAVE = kThreads / 64;
   static constexpr int WGROWS = WROWS * NWAVE;                      // rows per WG step
@@ -199,8 +207,240 @@ __device__ void write_partial(const double* red, int L, const RedCtl& rc) {
 }
 
 // ---------------------------------------------------------------------------
-// Small dense algebra on t x t matrices in LDS (row-major, leading dim TPI),
-// run by one work-group.
+// Small dense algebra on t x t matrices, run by one wave after the totals
+// are formed.  Matrices are row-major with leading dimension TPI, zero in
+// the padding.  Lane c holds column c of the matrix being formed in
+// registers (lanes c >= TPI are idle); the other operand of a product is
+// read from LDS or global memory, every lane reading the same element
+// (a broadcast).  Lanes exchange data only through LDS, ordered by wsync():
+// the wave's LDS accesses complete in program order, so a fence at wave
+// scope that keeps the compiler from reordering them is enough.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lanes c < TPI take part; the caller returns the others.
+template <int TPI>
+__device__ __forceinline__ void col_load(const double* M, int c, double (&x)[TPI]) {
+#pragma unroll
+  for (int i = 0; i < TPI; ++i) x[i] = M[i * TPI + c];
+}
+
+template <int TPI>
+__device__ __forceinline__ void col_store(double* M, int c, const double (&x)[TPI], double sc) {
+#pragma unroll
+  for (int i = 0; i < TPI; ++i) M[i * TPI + c] = sc * x[i];
+}
+
+// Copy a TPI x TPI matrix (global) into LDS.
+template <int TPI>
+__device__ __forceinline__ void mat_to_lds(const double* src, double* dst, int c) {
+#pragma unroll
+  for (int i = 0; i < TPI; ++i) dst[i * TPI + c] = src[i * TPI + c];
+}
+
+// y = op(A) x for lane c's column x, A in LDS; op(A) = A^t if TRANS.
+// Outer loop over k: the TPI accumulators are independent, so the FMAs of
+// one step issue back to back.
+template <int TPI, bool TRANS>
+__device__ __forceinline__ void col_mul(const double* A, const double (&x)[TPI], double (&y)[TPI]) {
+#pragma unroll
+  for (int i = 0; i < TPI; ++i) y[i] = 0.0;
+#pragma unroll
+  for (int k = 0; k < TPI; ++k) {
+    asm volatile("" ::: "memory");   // one column of op(A) in flight at a time
+#pragma unroll
+    for (int i = 0; i < TPI; ++i)
+      y[i] = __builtin_fma(TRANS ? A[k * TPI + i] : A[i * TPI + k], x[k], y[i]);
+  }
+}
+
+// Lane-uniform value of lane L's register (v_readlane).
+template <int L>
+__device__ __forceinline__ double lane_value(double v) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), L);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), L);
+  return __hiloint2double(hi, lo);
+}
+
+// Upper Cholesky G = R^t R of the leading t x t block, lane c holding
+// column c of G on entry and of R on return (zero below the diagonal and
+// in the padding).  Pivots and rows of R are read across lanes with
+// v_readlane.  A pivot <= 0 or not finite sets *bad and is replaced by 1
+// so that the factorisation runs to the end.
+template <int TPI>
+__device__ void w_chol(double (&g)[TPI], int t, int* bad) {
+  const int c = threadIdx.x & 63;
+  static_for<TPI>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    if (j >= t) {            // uniform: padding rows of R are zero
+      g[j] = 0.0;
+      return;
+    }
+    double d2 = lane_value<j>(g[j]);
+    if (!(d2 > 0.0) || !isfinite(d2)) {
+      *bad = 1;
+      d2 = 1.0;
+    }
+    const double d = sqrt(d2);
+    const double rj = c > j ? g[j] / d : (c == j ? d : 0.0);
+    const double rjc = c < t ? rj : 0.0;
+    // trailing update of the rows below j: G[i][c] -= R[j][i] R[j][c]
+    static_for<TPI - j - 1>([&](auto ic) {
+      constexpr int i = j + 1 + decltype(ic)::value;
+      g[i] = __builtin_fma(-lane_value<i>(rjc), rjc, g[i]);
+    });
+    g[j] = rjc;              // R[j][c]; zero for j > c
+  });
+}
+
+// Lane c: column c of R^{-1} (R upper triangular in LDS, t x t leading
+// block) by back substitution in column (axpy) order; zero in the padding.
+template <int TPI>
+__device__ void w_trinv(const double* R, int t, double (&x)[TPI]) {
+  const int c = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < TPI; ++i) x[i] = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+  for (int k = TPI - 1; k >= 0; --k) {
+    if (k >= t) {
+      x[k] = 0.0;
+      continue;
+    }
+    asm volatile("" ::: "memory");
+    x[k] = c < t ? x[k] / R[k * TPI + k] : 0.0;
+#pragma unroll
+    for (int i = 0; i < k; ++i) x[i] = __builtin_fma(-R[i * TPI + k], x[k], x[i]);
+  }
+}
+
+// Tail after the product A U_m with the Grams G = U^t AU, F = AU^t AU,
+// E = AU_{m-1}^t AU and a = U^t r (layout of `sums`: G | F | E | a).
+// Produces R_m^{-1}, the x/r coefficients beta_m = R^{-1} R^{-t} a, and the
+// coefficients of the next block's first CGS pass:
+//   C0 = R_m^{-1}, C1 = -R_m^{-1} H_m, C2 = -R_{m-1}^{-1} H_{m-1}
+// with H_m = R_m^{-t} F R_m^{-1}, H_{m-1} = R_{m-1}^{-t} E R_m^{-1}.
+// LDS: sums (3 TPI^2 + TPI) and tmp (2 TPI + TPI^2).
+template <int TPI>
+__device__ void tail_spmm(double* sums, double* tmp, const TailArgs& ta) {
+  constexpr int T2 = TPI * TPI;
+  const int c = threadIdx.x & 63, t = ta.t;
+  double* G = sums;
+  double* F = sums + T2;
+  double* E = sums + 2 * T2;
+  const double* a = sums + 3 * T2;
+  double* Rp = tmp + 2 * TPI;
+  const bool prev = ta.m >= 2 && ta.rinv_p1 != nullptr;
+  if (prev) mat_to_lds<TPI>(ta.rinv_p1, Rp, c);
+  int bad = 0;
+  double x[TPI], y[TPI], h[TPI];
+  col_load<TPI>(G, c, x);
+  wsync();
+  w_chol<TPI>(x, t, &bad);
+  col_store<TPI>(G, c, x, 1.0);               // G <- R
+  wsync();
+  w_trinv<TPI>(G, t, y);                      // y: column c of R^{-1}
+  wsync();
+  col_store<TPI>(G, c, y, 1.0);               // G <- R^{-1}
+  col_store<TPI>(ta.rinv_cur, c, y, 1.0);
+  col_store<TPI>(ta.cnext, c, y, 1.0);        // C0
+  // beta = R^{-1} (R^{-t} a): lane c forms (R^{-t} a)_c from its column
+  double al = 0.0;
+#pragma unroll
+  for (int k = 0; k < TPI; ++k) al = __builtin_fma(y[k], a[k], al);
+  tmp[TPI + c] = al;
+  wsync();
+  double b = 0.0;
+#pragma unroll
+  for (int k = 0; k < TPI; ++k) b = __builtin_fma(G[c * TPI + k], tmp[TPI + k], b);
+  ta.beta[c] = b;
+  // C1 = -R^{-1} R^{-t} F R^{-1}
+  col_mul<TPI, false>(F, y, x);               // x = F R^{-1} e_c
+  col_mul<TPI, true>(G, x, h);                // h = H_m e_c
+  col_mul<TPI, false>(G, h, x);
+  col_store<TPI>(ta.cnext + T2, c, x, -1.0);
+  if (prev) {
+    // C2 = -R_{m-1}^{-1} R_{m-1}^{-t} E R_m^{-1}
+    col_mul<TPI, false>(E, y, x);             // x = E R_m^{-1} e_c
+    col_mul<TPI, true>(Rp, x, h);
+    col_mul<TPI, false>(Rp, h, x);
+    col_store<TPI>(ta.cnext + 2 * T2, c, x, -1.0);
+  }
+  if (bad && c == 0 && ta.status->breakdown == 0) {   // the first failing block is kept
+    ta.status->breakdown = 1;
+    ta.status->breakdown_block = ta.m;
+  }
+}
+
+// Tail after the first CGS update: sums hold H2'_g = AU_g^t Z' (g < ng);
+// D_g = -R_g^{-1} R_g^{-t} H2'_g, where g = 0 is block m-1 and g = 1 block m-2.
+// LDS scratch: TPI^2.
+template <int TPI>
+__device__ void tail_cgs(double* sums, double* tmp, int ng, const TailArgs& ta) {
+  constexpr int T2 = TPI * TPI;
+  const int c = threadIdx.x & 63;
+  for (int g = 0; g < ng; ++g) {
+    mat_to_lds<TPI>(g == 0 ? ta.rinv_p1 : ta.rinv_p2, tmp, c);
+    double x[TPI], y[TPI];
+    col_load<TPI>(sums + g * T2, c, x);
+    wsync();
+    col_mul<TPI, true>(tmp, x, y);
+    col_mul<TPI, false>(tmp, y, x);
+    col_store<TPI>(ta.dcoef + g * T2, c, x, -1.0);
+    wsync();
+  }
+}
+
+// Tail for one chunk of earlier blocks (SRE-CG2, MSDO-CG): sums hold G_g
+// (g < ng); coef_out[g] = -R_g^{-1} R_g^{-t} G_g [R_right^{-1}].
+// LDS scratch: TPI^2.
+template <int TPI>
+__device__ void tail_gram(double* sums, double* tmp, int ng, const TailArgs& ta) {
+  constexpr int T2 = TPI * TPI;
+  const int c = threadIdx.x & 63;
+  double rr[TPI];
+  if (ta.rinv_right) col_load<TPI>(ta.rinv_right, c, rr);
+  for (int g = 0; g < ng; ++g) {
+    mat_to_lds<TPI>(ta.rinv_g[g], tmp, c);
+    double x[TPI], y[TPI];
+    if (ta.rinv_right) col_mul<TPI, false>(sums + g * T2, rr, x);   // G_g R_right^{-1} e_c
+    else col_load<TPI>(sums + g * T2, c, x);
+    wsync();
+    col_mul<TPI, true>(tmp, x, y);
+    col_mul<TPI, false>(tmp, y, x);
+    col_store<TPI>(ta.coef_out[g], c, x, -1.0);
+    wsync();
+  }
+}
+
+// Tail of Pre-CholQR: the Euclidean Gram Z^t Z = Re^t Re; Re^{-1} to
+// coef_out[0] (breakdown as for A-CholQR).  LDS scratch: TPI.
+template <int TPI>
+__device__ void tail_pre(double* sums, double* tmp, const TailArgs& ta) {
+  const int c = threadIdx.x & 63;
+  int bad = 0;
+  double x[TPI], y[TPI];
+  col_load<TPI>(sums, c, x);
+  wsync();
+  w_chol<TPI>(x, ta.t, &bad);
+  col_store<TPI>(sums, c, x, 1.0);
+  wsync();
+  w_trinv<TPI>(sums, ta.t, y);
+  col_store<TPI>(ta.coef_out[0], c, y, 1.0);
+  if (bad && c == 0 && ta.status->breakdown == 0) {
+    ta.status->breakdown = 1;
+    ta.status->breakdown_block = ta.m;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same tails run by the whole work-group on LDS-resident matrices, for
+// 32 and 64 stored columns (a lane would need 3 x TPI doubles of registers
+// for the one-wave form).
 // ---------------------------------------------------------------------------
 
 // In-place upper Cholesky G = R^t R of the leading t x t block (upper
@@ -208,7 +448,7 @@ __device__ void write_partial(const double* red, int L, const RedCtl& rc) {
 // On return the block holds R with zeros below the diagonal and in the
 // padding.
 template <int TPI>
-__device__ void chol_upper_inplace(double* G, int t, int* bad) {
+__device__ void b_chol(double* G, int t, int* bad) {
   const int tid = threadIdx.x;
   for (int j = 0; j < t; ++j) {
     if (tid == 0) {
@@ -240,7 +480,7 @@ __device__ void chol_upper_inplace(double* G, int t, int* bad) {
 
 // In-place inverse of the upper triangular leading t x t block.
 template <int TPI>
-__device__ void trinv_upper_inplace(double* R, int t, double* tmp) {
+__device__ void b_trinv(double* R, int t, double* tmp) {
   const int tid = threadIdx.x;
   for (int j = 0; j < t; ++j) {
     // column j of the inverse: X[i][j] = -X[j][j] * sum_{k=i}^{j-1} X[i][k] R[k][j]
@@ -261,7 +501,7 @@ __device__ void trinv_upper_inplace(double* R, int t, double* tmp) {
 // padding of C is zero.  Operands normally live in LDS; any of them may be
 // in global memory.
 template <int TPI>
-__device__ void small_mm(const double* A, bool ta, const double* B, double* C, int t,
+__device__ void b_mm(const double* A, bool ta, const double* B, double* C, int t,
                          double scale) {
   for (int idx = threadIdx.x; idx < TPI * TPI; idx += blockDim.x) {
     const int i = idx / TPI, c = idx % TPI;
@@ -275,7 +515,7 @@ __device__ void small_mm(const double* A, bool ta, const double* B, double* C, i
 }
 
 template <int TPI>
-__device__ void copy_mat(const double* src, double* dst) {
+__device__ void b_copy(const double* src, double* dst) {
   for (int idx = threadIdx.x; idx < TPI * TPI; idx += blockDim.x) dst[idx] = src[idx];
   __syncthreads();
 }
@@ -287,7 +527,7 @@ __device__ void copy_mat(const double* src, double* dst) {
 //   C0 = R_m^{-1}, C1 = -R_m^{-1} H_m, C2 = -R_{m-1}^{-1} H_{m-1}
 // with H_m = R_m^{-t} F R_m^{-1}, H_{m-1} = R_{m-1}^{-t} E R_m^{-1}.
 template <int TPI>
-__device__ void tail_spmm(double* sums, double* tmp, const TailArgs& ta) {
+__device__ void btail_spmm(double* sums, double* tmp, const TailArgs& ta) {
   constexpr int T2 = TPI * TPI;
   __shared__ int s_bad;
   const int t = ta.t, tid = threadIdx.x;
@@ -297,8 +537,8 @@ __device__ void tail_spmm(double* sums, double* tmp, const TailArgs& ta) {
   double* a = sums + 3 * T2;
   if (tid == 0) s_bad = 0;
   __syncthreads();
-  chol_upper_inplace<TPI>(G, t, &s_bad);
-  trinv_upper_inplace<TPI>(G, t, tmp);           // G now holds R^{-1}
+  b_chol<TPI>(G, t, &s_bad);
+  b_trinv<TPI>(G, t, tmp);           // G now holds R^{-1}
   for (int idx = tid; idx < T2; idx += blockDim.x) {
     ta.rinv_cur[idx] = G[idx];
     ta.cnext[idx] = G[idx];                      // C0
@@ -319,14 +559,14 @@ __device__ void tail_spmm(double* sums, double* tmp, const TailArgs& ta) {
   }
   __syncthreads();
   // H_m = R^{-t} F R^{-1}; C1 = -R^{-1} H_m
-  small_mm<TPI>(F, false, G, tmp, t, 1.0);       // tmp = F R^{-1}
-  small_mm<TPI>(G, true, tmp, F, t, 1.0);        // F <- H_m
-  small_mm<TPI>(G, false, F, ta.cnext + T2, t, -1.0);
+  b_mm<TPI>(F, false, G, tmp, t, 1.0);       // tmp = F R^{-1}
+  b_mm<TPI>(G, true, tmp, F, t, 1.0);        // F <- H_m
+  b_mm<TPI>(G, false, F, ta.cnext + T2, t, -1.0);
   if (ta.m >= 2 && ta.rinv_p1 != nullptr) {
-    small_mm<TPI>(E, false, G, tmp, t, 1.0);     // tmp = E R_m^{-1}
-    copy_mat<TPI>(ta.rinv_p1, E);                // E <- R_{m-1}^{-1}
-    small_mm<TPI>(E, true, tmp, F, t, 1.0);      // F <- H_{m-1}
-    small_mm<TPI>(E, false, F, ta.cnext + 2 * T2, t, -1.0);
+    b_mm<TPI>(E, false, G, tmp, t, 1.0);     // tmp = E R_m^{-1}
+    b_copy<TPI>(ta.rinv_p1, E);                // E <- R_{m-1}^{-1}
+    b_mm<TPI>(E, true, tmp, F, t, 1.0);      // F <- H_{m-1}
+    b_mm<TPI>(E, false, F, ta.cnext + 2 * T2, t, -1.0);
   }
   if (tid == 0 && s_bad && ta.status->breakdown == 0) {
     ta.status->breakdown = 1;
@@ -337,33 +577,33 @@ __device__ void tail_spmm(double* sums, double* tmp, const TailArgs& ta) {
 // Tail after the first CGS update: sums hold H2'_g = AU_g^t Z' (g < ng);
 // D_g = -R_g^{-1} R_g^{-t} H2'_g, where g = 0 is block m-1 and g = 1 block m-2.
 template <int TPI>
-__device__ void tail_cgs(double* sums, double* tmp, int ng, const TailArgs& ta) {
+__device__ void btail_cgs(double* sums, double* tmp, int ng, const TailArgs& ta) {
   constexpr int T2 = TPI * TPI;
   double* Rs = tmp;
   double* T = tmp + T2;
   for (int g = 0; g < ng; ++g) {
-    copy_mat<TPI>(g == 0 ? ta.rinv_p1 : ta.rinv_p2, Rs);
-    small_mm<TPI>(Rs, true, sums + g * T2, T, ta.t, 1.0);
-    small_mm<TPI>(Rs, false, T, ta.dcoef + g * T2, ta.t, -1.0);
+    b_copy<TPI>(g == 0 ? ta.rinv_p1 : ta.rinv_p2, Rs);
+    b_mm<TPI>(Rs, true, sums + g * T2, T, ta.t, 1.0);
+    b_mm<TPI>(Rs, false, T, ta.dcoef + g * T2, ta.t, -1.0);
   }
 }
 
 // Tail for one chunk of earlier blocks (SRE-CG2): sums hold G_g (g < ng);
 // coef_out[g] = -R_g^{-1} (R_g^{-t} G_g [R_right^{-1}]).
 template <int TPI>
-__device__ void tail_gram(double* sums, double* tmp, int ng, const TailArgs& ta) {
+__device__ void btail_gram(double* sums, double* tmp, int ng, const TailArgs& ta) {
   constexpr int T2 = TPI * TPI;
   double* Rs = tmp;
   double* T = tmp + T2;
   for (int g = 0; g < ng; ++g) {
-    copy_mat<TPI>(ta.rinv_g[g], Rs);
-    small_mm<TPI>(Rs, true, sums + g * T2, T, ta.t, 1.0);      // T = R_g^{-t} G_g
+    b_copy<TPI>(ta.rinv_g[g], Rs);
+    b_mm<TPI>(Rs, true, sums + g * T2, T, ta.t, 1.0);      // T = R_g^{-t} G_g
     if (ta.rinv_right) {
       // G_g <- T R_right^{-1} (the right factor is read from global memory)
-      small_mm<TPI>(T, false, ta.rinv_right, sums + g * T2, ta.t, 1.0);
-      small_mm<TPI>(Rs, false, sums + g * T2, ta.coef_out[g], ta.t, -1.0);
+      b_mm<TPI>(T, false, ta.rinv_right, sums + g * T2, ta.t, 1.0);
+      b_mm<TPI>(Rs, false, sums + g * T2, ta.coef_out[g], ta.t, -1.0);
     } else {
-      small_mm<TPI>(Rs, false, T, ta.coef_out[g], ta.t, -1.0);
+      b_mm<TPI>(Rs, false, T, ta.coef_out[g], ta.t, -1.0);
     }
   }
 }
@@ -371,12 +611,12 @@ __device__ void tail_gram(double* sums, double* tmp, int ng, const TailArgs& ta)
 // Tail of Pre-CholQR: the Euclidean Gram Z^t Z = Re^t Re; Re^{-1} to
 // coef_out[0] (breakdown as for A-CholQR).
 template <int TPI>
-__device__ void tail_pre(double* sums, double* tmp, const TailArgs& ta) {
+__device__ void btail_pre(double* sums, double* tmp, const TailArgs& ta) {
   __shared__ int s_bad;
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
-  chol_upper_inplace<TPI>(sums, ta.t, &s_bad);
-  trinv_upper_inplace<TPI>(sums, ta.t, tmp);
+  b_chol<TPI>(sums, ta.t, &s_bad);
+  b_trinv<TPI>(sums, ta.t, tmp);
   for (int idx = threadIdx.x; idx < TPI * TPI; idx += blockDim.x) ta.coef_out[0][idx] = sums[idx];
   if (threadIdx.x == 0 && s_bad && ta.status->breakdown == 0) {
     ta.status->breakdown = 1;
@@ -442,7 +682,7 @@ __global__ __launch_bounds__(kThreads) void k_tsplit(const double* __restrict__ 
 // (the first CGS pass of block m uses A U_{m-1} both ways); it is loaded once.
 template <int TPI, typename S, int NU, int NG, bool IDENT0, bool WRITE, int TAIL, bool P0X>
 __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
-  using C = Cfg<TPI>;
+  using C = Cfg<TPI, S>;
   constexpr int EPL = C::EPL, RPL = C::RPL, T2 = C::T2;
   constexpr int NCOEF = NU - (IDENT0 ? 1 : 0);
   constexpr int NX = NU;                         // loaded update operands (incl. X0)
@@ -583,10 +823,11 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
 // E = AZprev^t AZ and a = Z^t r.
 constexpr int kChunk = ECG_SP_CHUNK;   // <= 16
 
-template <int TPI>
+template <int TPI, typename S = double>
 struct SpCfg {
   static constexpr int EPL = TPI / 16;
-  static constexpr int RPL = TPI == 16 ? ECG_SP_RPL16 : (TPI == 32 ? 2 : 1);
+  static constexpr int RPL = (TPI == 16 ? ECG_SP_RPL16 : (TPI == 32 ? 2 : 1)) *
+                             (sizeof(S) == 4 ? ECG_F32_SP_RPL_MUL : 1);
   static constexpr int WROWS = 4 * RPL;
   static constexpr int NWAVE = kThreads / 64;
   static constexpr int WGROWS = WROWS * NWAVE;
@@ -594,7 +835,7 @@ struct SpCfg {
 
 template <int TPI, typename S, typename SA, bool GRAMS, bool HAS_PREV, int TAIL>
 __global__ ECG_SPMM_ATTR void k_spmm(SpArgs<S, SA> a) {
-  using C = SpCfg<TPI>;
+  using C = SpCfg<TPI, S>;
   constexpr int EPL = C::EPL, RPL = C::RPL, T2 = TPI * TPI;
   constexpr int L = 3 * T2 + TPI;
   constexpr int LDSN = GRAMS ? L : 1;
@@ -1198,9 +1439,12 @@ __global__ __launch_bounds__(kThreads) void k_final(const double* __restrict__ g
                                                     int ngroups, int L, TailArgs ta) {
   constexpr int T2 = TPI * TPI;
   constexpr int LSP = 3 * T2 + TPI;
-  constexpr int LDSN = TAIL == TAIL_SPMM ? LSP + T2
-                       : (TAIL == TAIL_CGS ? (NG + 2) * T2
-                       : (TAIL == TAIL_GRAM ? (NG + 2) * T2 : (TAIL == TAIL_PRE ? 2 * T2 : 8)));
+  // one-wave tails (16 columns): the sums and 2 TPI of scratch; the
+  // work-group tails: the sums and one or two t x t scratch matrices
+  constexpr bool WAVE = TPI == 16;
+  constexpr int LDSN = TAIL == TAIL_SPMM ? LSP + (WAVE ? 2 * TPI + T2 : T2)
+                       : (TAIL == TAIL_CGS || TAIL == TAIL_GRAM ? (NG + (WAVE ? 1 : 2)) * T2
+                       : (TAIL == TAIL_PRE ? T2 + (WAVE ? TPI : T2) : 8));
   __shared__ double lds[LDSN];
   // entries four at a time, group sums sixteen at a time: up to 64 loads in
   // flight per thread; each entry is still summed in group order
@@ -1226,6 +1470,22 @@ __global__ __launch_bounds__(kThreads) void k_final(const double* __restrict__ g
   __syncthreads();
   if (ta.sums_out)
     for (int i = threadIdx.x; i < L; i += blockDim.x) ta.sums_out[i] = lds[i];
+  if constexpr (TPI > 16 && TAIL != TAIL_NORM) {
+    // whole work-group on LDS (the sums region is followed by scratch)
+    if constexpr (TAIL == TAIL_SPMM) btail_spmm<TPI>(lds, lds + LSP, ta);
+    else if constexpr (TAIL == TAIL_CGS) btail_cgs<TPI>(lds, lds + NG * T2, NG, ta);
+    else if constexpr (TAIL == TAIL_GRAM) btail_gram<TPI>(lds, lds + NG * T2, NG, ta);
+    else if constexpr (TAIL == TAIL_PRE) btail_pre<TPI>(lds, lds + T2, ta);
+    return;
+  }
+  if constexpr (TAIL == TAIL_NORM) {
+    if (threadIdx.x == 0) {
+      if (ta.which == 0) ta.status->rho = sqrt(lds[0]);
+      else ta.status->rho_true = sqrt(lds[0]);
+    }
+    return;
+  }
+  if (threadIdx.x >= TPI) return;   // the small algebra: lanes 0 .. TPI-1 of wave 0
   if constexpr (TAIL == TAIL_SPMM) {
     tail_spmm<TPI>(lds, lds + LSP, ta);
   } else if constexpr (TAIL == TAIL_CGS) {
@@ -1234,11 +1494,6 @@ __global__ __launch_bounds__(kThreads) void k_final(const double* __restrict__ g
     tail_gram<TPI>(lds, lds + NG * T2, NG, ta);
   } else if constexpr (TAIL == TAIL_PRE) {
     tail_pre<TPI>(lds, lds + T2, ta);
-  } else if constexpr (TAIL == TAIL_NORM) {
-    if (threadIdx.x == 0) {
-      if (ta.which == 0) ta.status->rho = sqrt(lds[0]);
-      else ta.status->rho_true = sqrt(lds[0]);
-    }
   }
 }
 
