@@ -82,6 +82,15 @@ struct UGArgs {
   int64_t n;
   RedCtl rc;
   TailArgs tail;
+  // Optional x/r contribution of the previous block, whose A-image and
+  // block are X[0] and X[1]: x_out = x_in + X[1] beta, r_out = r_in - X[0] beta
+  // (fold_beta == nullptr: none; skipped after a breakdown).
+  const double* fold_beta;
+  const double* x_in;
+  double* x_out;
+  const double* r_in;
+  double* r_out;
+  const DevStatus* status;
 };
 
 template <typename S, typename SA>
@@ -104,8 +113,10 @@ struct XRArgs {
   const S* AU[kMaxS];
   const double* beta[kMaxS];   // [TPI] each
   int nb;
-  double* x;
-  double* r;
+  const double* x_in;          // x_out = x_in + sum U_i beta_i (may alias)
+  const double* r_in;          // r_out = r_in - sum AU_i beta_i (may alias)
+  double* x;                   // x_out
+  double* r;                   // r_out
   int64_t n;
   const DevStatus* status_in;  // skip everything after a breakdown
   RedCtl rc;

@@ -61,6 +61,17 @@ __device__ __forceinline__ double bcast64(double v) {
   return __builtin_amdgcn_update_dpp(v, v, 0x150 + N, 0xF, 0xF, true);
 }
 
+// Sum over the 16 lanes of each DPP row, result in every lane of the row:
+// pairs (quad_perm 1,0,3,2), quads (2,3,0,1), half rows (row_half_mirror),
+// rows (row_mirror); no LDS traffic.
+__device__ __forceinline__ double row_sum16(double v) {
+  v += __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false);
+  return v;
+}
+
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -692,6 +703,7 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
   constexpr int TAILSZ = NG * T2;
   constexpr int LDSN = (BODY > TAILSZ ? BODY : TAILSZ) > 1 ? (BODY > TAILSZ ? BODY : TAILSZ) : 1;
   __shared__ double lds[LDSN];
+  __shared__ double fbeta[TPI];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m = lane & 15, rq = lane >> 4;
@@ -700,6 +712,10 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
     const double* src = a.C[b + (IDENT0 ? 1 : 0)];
     for (int idx = tid; idx < T2; idx += blockDim.x) lds[b * T2 + idx] = src[idx];
   }
+  // fold of the previous block's x/r contribution (uniform)
+  const bool fold = !IDENT0 && NU >= 2 && a.fold_beta != nullptr && a.status->breakdown == 0;
+  if (fold)
+    for (int idx = tid; idx < TPI; idx += blockDim.x) fbeta[idx] = a.fold_beta[idx];
   __syncthreads();
 
   d4 acc[NG > 0 ? NG : 1][EPL][EPL];
@@ -712,8 +728,10 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
   for (int g = 0; g < NP; ++g) src[NX + g] = a.P[g + (P0X ? 1 : 0)];
 
   const int64_t n = a.n;
-  // operands of one wave step: [operand][q][e], zero on rows >= n
-  auto load_step = [&](int64_t step, double (&v)[NLD][RPL][EPL]) {
+  // operands of one wave step: [operand][q][e], zero on rows >= n; with the
+  // fold also x and r of the rows
+  auto load_step = [&](int64_t step, double (&v)[NLD][RPL][EPL], double (&vx)[RPL],
+                       double (&vr)[RPL]) {
     const int64_t row0 = step * C::WGROWS + wave * C::WROWS + rq;
     for (int q = 0; q < RPL; ++q) {
       const int64_t row = row0 + 4 * q;
@@ -721,22 +739,47 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
       const double okf = opaque(row < n ? 1.0 : 0.0);
       for (int b = 0; b < NLD; ++b)
         for (int e = 0; e < EPL; ++e) v[b][q][e] = ld(src[b] + rc * TPI + m + 16 * e) * okf;
+      if (fold) {
+        vx[q] = a.x_in[rc];
+        vr[q] = a.r_in[rc];
+      }
     }
   };
 
   constexpr bool PF = ECG_UG_PREFETCH != 0;
   double cur[NLD][RPL][EPL], nxt[PF ? NLD : 1][RPL][EPL];
+  double fx[RPL], fr[RPL], nfx[RPL], nfr[RPL];
   const Steps sp = my_steps((n + C::WGROWS - 1) / C::WGROWS);
   int64_t step = sp.first;
   bool have = step < sp.end;
-  if (have) load_step(step, cur);
+  if (have) load_step(step, cur, fx, fr);
   while (have) {
     const int64_t nstep = step + sp.stride;
     const bool have_next = nstep < sp.end;
     if constexpr (PF) {
-      if (have_next) load_step(nstep, nxt);
+      if (have_next) load_step(nstep, nxt, nfx, nfr);
     }
 
+    if constexpr (!IDENT0 && NU >= 2) {
+      if (fold) {
+        const int64_t row0f = step * C::WGROWS + wave * C::WROWS + rq;
+        for (int q = 0; q < RPL; ++q) {
+          double dx = 0.0, dr = 0.0;
+          for (int e = 0; e < EPL; ++e) {
+            const double bv = fbeta[m + 16 * e];
+            dx = __builtin_fma(cur[1][q][e], bv, dx);
+            dr = __builtin_fma(cur[0][q][e], bv, dr);
+          }
+          dx = row_sum16(dx);
+          dr = row_sum16(dr);
+          const int64_t row = row0f + 4 * q;
+          if (m == 0 && row < n) {
+            a.x_out[row] = fx[q] + dx;
+            a.r_out[row] = fr[q] - dr;
+          }
+        }
+      }
+    }
     double o[RPL][EPL];
     for (int q = 0; q < RPL; ++q)
       for (int e = 0; e < EPL; ++e) o[q][e] = IDENT0 ? cur[0][q][e] : 0.0;
@@ -792,9 +835,13 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
         for (int b = 0; b < NLD; ++b)
           for (int q = 0; q < RPL; ++q)
             for (int e = 0; e < EPL; ++e) cur[b][q][e] = nxt[b][q][e];
+        for (int q = 0; q < RPL; ++q) {
+          fx[q] = nfx[q];
+          fr[q] = nfr[q];
+        }
       }
     } else {
-      if (have_next) load_step(nstep, cur);
+      if (have_next) load_step(nstep, cur, fx, fr);
     }
     step = nstep;
     have = have_next;
@@ -1057,6 +1104,10 @@ void k_update_gram_cs(UGArgs<S> a) {
     const double* src = a.C[b + (IDENT0 ? 1 : 0)];
     for (int idx = tid; idx < T2; idx += blockDim.x) lds[b * T2 + idx] = src[idx];
   }
+  __shared__ double fbeta[TPI];
+  const bool fold = !IDENT0 && NU >= 2 && a.fold_beta != nullptr && a.status->breakdown == 0;
+  if (fold)
+    for (int idx = tid; idx < TPI; idx += blockDim.x) fbeta[idx] = a.fold_beta[idx];
   __syncthreads();
 
   d4 acc[NG > 0 ? NG : 1][EPL];
@@ -1078,6 +1129,33 @@ void k_update_gram_cs(UGArgs<S> a) {
       const double okf = opaque(row < n ? 1.0 : 0.0);
       for (int b = 0; b < NLD; ++b)
         for (int e = 0; e < EPL; ++e) cur[b][q][e] = ld(src[b] + rc * TPI + m + 16 * e) * okf;
+    }
+    if constexpr (!IDENT0 && NU >= 2) {
+      // every wave of the row group holds the full rows; column block 0 folds
+      if (fold && cb == 0) {
+        double xo[RPL], ro[RPL];
+        for (int q = 0; q < RPL; ++q) {
+          const int64_t row = row0 + 4 * q;
+          const int64_t rc = row < n ? row : n - 1;
+          xo[q] = a.x_in[rc];
+          ro[q] = a.r_in[rc];
+        }
+        for (int q = 0; q < RPL; ++q) {
+          double dx = 0.0, dr = 0.0;
+          for (int e = 0; e < EPL; ++e) {
+            const double bv = fbeta[m + 16 * e];
+            dx = __builtin_fma(cur[1][q][e], bv, dx);
+            dr = __builtin_fma(cur[0][q][e], bv, dr);
+          }
+          dx = row_sum16(dx);
+          dr = row_sum16(dr);
+          const int64_t row = row0 + 4 * q;
+          if (m == 0 && row < n) {
+            a.x_out[row] = xo[q] + dx;
+            a.r_out[row] = ro[q] - dr;
+          }
+        }
+      }
     }
     // NCH independent accumulation chains per row (the k-blocks of all
     // coefficient matrices in turn): one chain would serialise NCOEF * TPI
@@ -1293,11 +1371,12 @@ void k_spmm_cs(SpArgs<S, SA> a) {
 
 // x += sum_i U_i beta_i ; r -= sum_i AU_i beta_i ; ||r||^2.  Blocks are
 // taken four at a time so that eight loads per row are in flight.
-template <int TPI, typename S>
+template <int TPI, typename S, int NB4>
 __global__ ECG_STREAM void k_xr(XRArgs<S> a) {
-  constexpr int EPL = TPI / 16, RPL = TPI == 16 ? 4 : (TPI == 32 ? 2 : 1);
+  // NB4 blocks per pass; a single block gets twice the row quads instead
+  constexpr int EPL = TPI / 16, RPL = (TPI == 16 ? 4 : (TPI == 32 ? 2 : 1)) * (NB4 == 1 ? 2 : 1);
   constexpr int WROWS = 4 * RPL, NWAVE = kThreads / 64;
-  constexpr int WGROWS = WROWS * NWAVE, NB4 = 4;
+  constexpr int WGROWS = WROWS * NWAVE;
   __shared__ double bl[kMaxS * TPI];
   __shared__ double red[8];
   if (a.status_in->breakdown) return;     // uniform: the host stops after this iteration
@@ -1319,8 +1398,8 @@ __global__ ECG_STREAM void k_xr(XRArgs<S> a) {
       ok[q] = row < n;
       rowc[q] = ok[q] ? row : n - 1;
       // issued with the block loads; only lane m = 0 of a row uses them
-      xo[q] = a.x[rowc[q]];
-      ro[q] = a.r[rowc[q]];
+      xo[q] = a.x_in[rowc[q]];
+      ro[q] = a.r_in[rowc[q]];
     }
     double dx[RPL], dr[RPL];
     for (int q = 0; q < RPL; ++q) {
@@ -1347,10 +1426,8 @@ __global__ ECG_STREAM void k_xr(XRArgs<S> a) {
         }
     }
     for (int q = 0; q < RPL; ++q) {
-      for (int off = 8; off > 0; off >>= 1) {
-        dx[q] += __shfl_xor(dx[q], off, 16);
-        dr[q] += __shfl_xor(dr[q], off, 16);
-      }
+      dx[q] = row_sum16(dx[q]);
+      dr[q] = row_sum16(dr[q]);
       const double rn = ro[q] - dr[q];
       if (m == 0 && ok[q]) {
         a.x[rowc[q]] = xo[q] + dx[q];
@@ -1641,7 +1718,10 @@ hipError_t launch_spmm(bool grams, bool has_prev, int tail, const SpArgs<S, SA>&
 
 template <int TPI, typename S>
 hipError_t launch_xr(const XRArgs<S>& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_xr<TPI, S>), dim3(grid), dim3(kThreads), 0, st, a);
+  if (a.nb == 1)
+    hipLaunchKernelGGL((k_xr<TPI, S, 1>), dim3(grid), dim3(kThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_xr<TPI, S, 4>), dim3(grid), dim3(kThreads), 0, st, a);
   return hipGetLastError();
 }
 

@@ -73,8 +73,10 @@ struct ecg_ctx {
   double* vals = nullptr;
   float* vals32 = nullptr;
   double* b = nullptr;
-  double* x = nullptr;
-  double* r = nullptr;
+  double* x = nullptr;        // last completed iterate
+  double* r = nullptr;        // its recursive residual
+  double* x2 = nullptr;       // the iterate being formed (swapped with x per iteration)
+  double* r2 = nullptr;
 
   int nslot = 0;              // block slots (SRE-CG2: the block cap)
   int nalloc = 0;             // slots with allocated U / AU
@@ -253,7 +255,7 @@ extern "C" void ecg_destroy(ecg_ctx* c) {
     if (p) (void)hipFree(p);
   };
   f(c->rowptr); f(c->colind); f(c->dom); f(c->vals); f(c->vals32);
-  f(c->b); f(c->x); f(c->r);
+  f(c->b); f(c->x); f(c->r); f(c->x2); f(c->r2);
   for (void* p : c->U) f(p);
   for (void* p : c->AU) f(p);
   f(c->Zp); f(c->rinv); f(c->beta); f(c->cnext); f(c->dcoef);
@@ -401,7 +403,7 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   // ---- workspace size check ----
   const size_t esz = c->sbytes;
   const double fixed = blk * esz + (double)nnz * (4 + 8 + (o.precision ? 4 : 0)) +
-                       4.0 * (n + 1) + 4.0 * n + 3.0 * 8 * n + (double)max_partials * L * 8 +
+                       4.0 * (n + 1) + 4.0 * n + 5.0 * 8 * n + (double)max_partials * L * 8 +
                        (double)ngroups * L * 8;
   const double per_slot = 2.0 * blk * esz + 8.0 * (3.0 * T2 + tpi);
   size_t freeb = 0, totalb = 0;
@@ -445,6 +447,8 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   ALLOC(c->b, double, n);
   ALLOC(c->x, double, n);
   ALLOC(c->r, double, n);
+  ALLOC(c->x2, double, n);
+  ALLOC(c->r2, double, n);
   if (o.precision == ECG_MIXED) ALLOC(c->vals32, float, nnz);
   // SRE-CG2 keeps one block pair per block since the last restart; its
   // pairs are allocated when a solve first needs them (grow_slots)
@@ -509,9 +513,28 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
 
 namespace {
 
+// x/r contribution of the previous block carried by the next block's first
+// CGS kernel (which reads that block and its A-image anyway).
+struct Fold {
+  const double* beta;
+  const double* x_in;
+  const double* r_in;
+};
+
 template <int TPI, typename S, typename SA>
 struct Engine {
   ecg_ctx* c;
+
+  template <typename A>
+  void set_fold(A& a, const Fold* f) const {
+    if (!f) return;
+    a.fold_beta = f->beta;
+    a.x_in = f->x_in;
+    a.r_in = f->r_in;
+    a.x_out = c->x2;
+    a.r_out = c->r2;
+    a.status = c->status;
+  }
   const SA* avals() const {
     if constexpr (std::is_same<SA, float>::value) return c->vals32;
     else return c->vals;
@@ -569,7 +592,7 @@ struct Engine {
   // chunks of at most CH earlier blocks per launch.  Blocks m-1 and m-2 take
   // their first-pass coefficients from the product tail of block m-1, the
   // older ones from Gram chunks against A U_{m-1}.
-  int cgs_all(int m, int slot) {
+  int cgs_all(int m, int slot, const Fold* fold) {
     constexpr int T2 = TPI * TPI;
     constexpr int CH = TPI == 64 ? 2 : 3;
     const double bb = c->blk_bytes();
@@ -606,7 +629,10 @@ struct Engine {
       u.out = (S*)c->Zp;
       u.n = c->n;
       u.rc = c->rc();
-      if ((rc = ug(ECG_K_UPDATE, 3, 0, false, true, u, 4.0 * bb, 6.0 * nt2))) return rc;
+      set_fold(u, fold);
+      if ((rc = ug(ECG_K_UPDATE, 3, 0, false, true, u, 4.0 * bb + (fold ? 32.0 * c->n : 0.0),
+                   6.0 * nt2)))
+        return rc;
     }
     for (int p0 = 0; p0 <= m - 4; p0 += CH) {
       const int len = std::min(CH, m - 3 - p0);
@@ -724,14 +750,14 @@ struct Engine {
   // Build block m (1-based since the last restart) into `slot`; p1, p2 are
   // the slots of blocks m-1 and m-2; `first`: the first block of an s-step
   // iteration.
-  int block(int m, int slot, int p1, int p2, bool first) {
+  int block(int m, int slot, int p1, int p2, bool first, const Fold* fold) {
     const double bb = c->blk_bytes();
     const double nt2 = (double)c->n * c->t * c->t;
     if (c->o.variant == ECG_MSDO && first && m >= 2) {
       int rc = msdo_first(m, slot);
       if (rc) return rc;
     } else if (c->o.variant != ECG_SRECG && m >= 4) {
-      int rc = cgs_all(m, slot);
+      int rc = cgs_all(m, slot, fold);
       if (rc) return rc;
     } else if (m == 1) {
       Timed tm;
@@ -755,8 +781,10 @@ struct Engine {
       ka.tail = tail0(m);
       ka.tail.rinv_p1 = rinv(p1);
       ka.tail.rinv_p2 = np == 2 ? rinv(p2) : nullptr;
+      set_fold(ka, fold);
       Timed tm;
-      c->tstart(tm, ECG_K_CGS_GRAM, (2.0 * np + 1.0) * bb, 2.0 * nt2 * (2 * np + 1 + np));
+      c->tstart(tm, ECG_K_CGS_GRAM, (2.0 * np + 1.0) * bb + (fold ? 32.0 * c->n : 0.0),
+                2.0 * nt2 * (2 * np + 1 + np));
       HIP_TRY((launch_update_gram<TPI, S>(np + 1, np, false, true, TAIL_CGS, ka, c->grid, c->st)));
       c->tstop(tm);
       int rc = reduce(gram_partials(TPI, c->grid), np * TPI * TPI, TAIL_CGS, np, ka.tail);
@@ -804,7 +832,8 @@ struct Engine {
     return reduce(gram_partials(TPI, c->grid), 3 * TPI * TPI + TPI, TAIL_SPMM, 0, sa.tail);
   }
 
-  int xr(const int* slots, int nb) {
+  // x2 = x_in + sum U beta, r2 = r_in - sum AU beta over the given blocks, and ||r2||
+  int xr(const int* slots, int nb, const double* x_in, const double* r_in) {
     XRArgs<S> xa{};
     for (int i = 0; i < nb; ++i) {
       xa.U[i] = U(slots[i]);
@@ -812,8 +841,10 @@ struct Engine {
       xa.beta[i] = beta(slots[i]);
     }
     xa.nb = nb;
-    xa.x = c->x;
-    xa.r = c->r;
+    xa.x_in = x_in;
+    xa.r_in = r_in;
+    xa.x = c->x2;
+    xa.r = c->r2;
     xa.n = c->n;
     xa.status_in = c->status;
     xa.rc = c->rc();
@@ -893,16 +924,29 @@ struct Engine {
           slot_of[2] = slot_of[1];
           slot_of[1] = slot_of[0];
           slot_of[0] = slot;
-          if ((rc = block(m, slot, slot_of[1], slot_of[2], i == 0))) return rc;
+          // blocks after the first of an iteration carry the x/r
+          // contribution of the block before them
+          Fold f{};
+          if (i >= 1) {
+            f.beta = beta(slots[i - 1]);
+            f.x_in = i == 1 ? c->x : c->x2;
+            f.r_in = i == 1 ? c->r : c->r2;
+          }
+          if ((rc = block(m, slot, slot_of[1], slot_of[2], i == 0, i >= 1 ? &f : nullptr)))
+            return rc;
           slots[i] = slot;
           ++nblocks;
         }
-        if ((rc = xr(slots, c->s))) return rc;
+        // the last block's contribution; x2, r2 then hold the new iterate
+        if ((rc = xr(&slots[c->s - 1], 1, c->s == 1 ? c->x : c->x2, c->s == 1 ? c->r : c->r2)))
+          return rc;
         if ((rc = read_status(&h))) return rc;
-        if (h.breakdown) {
+        if (h.breakdown) {       // x, r stay the last completed iterate
           status = ECG_BREAKDOWN;
           break;
         }
+        std::swap(c->x, c->x2);
+        std::swap(c->r, c->r2);
         rho = h.rho;
         ++k;
         push(rho);
