@@ -61,6 +61,12 @@ __device__ __forceinline__ double bcast64(double v) {
   return __builtin_amdgcn_update_dpp(v, v, 0x150 + N, 0xF, 0xF, true);
 }
 
+// Value of lane (16 * (lane / 16) + N) of a 32-bit register.
+template <int N>
+__device__ __forceinline__ int bcast32(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x150 + N, 0xF, 0xF, true);
+}
+
 // Sum over the 16 lanes of each DPP row, result in every lane of the row:
 // pairs (quad_perm 1,0,3,2), quads (2,3,0,1), half rows (row_half_mirror),
 // rows (row_mirror); no LDS traffic.
@@ -148,6 +154,16 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #endif
 #ifndef ECG_SP_CHUNK
 #define ECG_SP_CHUNK 8
+#endif
+#ifndef ECG_SP_OFF32
+#define ECG_SP_OFF32 0         // 32-bit gather offsets when the block spans < 4 GiB
+#endif
+#ifndef ECG_SP_DEEP
+#define ECG_SP_DEEP 1          // deeper-pipelined product kernel at 16 columns: 1 for
+                               // binary32 blocks (faster there), 2 always, 0 never
+#endif
+#ifndef ECG_SP_DRPL
+#define ECG_SP_DRPL 2          // its row quads per lane
 #endif
 #ifndef ECG_CS_RPL
 #define ECG_CS_RPL 2           // row quads per lane of the column-split kernels
@@ -880,7 +896,9 @@ struct SpCfg {
   static constexpr int WGROWS = WROWS * NWAVE;
 };
 
-template <int TPI, typename S, typename SA, bool GRAMS, bool HAS_PREV, int TAIL>
+// OFF32: the block spans less than 4 GiB, so gathered rows are addressed by
+// a 32-bit byte offset from the block's base (one register per address).
+template <int TPI, typename S, typename SA, bool GRAMS, bool HAS_PREV, int TAIL, bool OFF32>
 __global__ ECG_SPMM_ATTR void k_spmm(SpArgs<S, SA> a) {
   using C = SpCfg<TPI, S>;
   constexpr int EPL = C::EPL, RPL = C::RPL, T2 = TPI * TPI;
@@ -912,7 +930,8 @@ __global__ ECG_SPMM_ATTR void k_spmm(SpArgs<S, SA> a) {
     int p0[RPL], p1[RPL];
   };
   struct Head {                 // first chunk of every row: lane m holds entry m % kChunk
-    double offb[RPL], valb[RPL];
+    double offb[OFF32 ? 1 : RPL], valb[RPL];
+    int offw[OFF32 ? RPL : 1];
   };
   auto load_rowptr = [&](int64_t step, RowPtr& rp) {
     const int64_t row0 = step * C::WGROWS + wave * C::WROWS + rq;
@@ -931,7 +950,10 @@ __global__ ECG_SPMM_ATTR void k_spmm(SpArgs<S, SA> a) {
       const int64_t msk = opaque((int64_t)(idx < rp.p1[q] ? -1 : 0));
       const double okf = opaque(idx < rp.p1[q] ? 1.0 : 0.0);
       const int64_t col = ld_s(a.colind + idc);
-      h.offb[q] = __builtin_bit_cast(double, (int64_t)(col * TPI) & msk);
+      if constexpr (OFF32)
+        h.offw[q] = (int)(((uint32_t)col * (uint32_t)(TPI * sizeof(S))) & (uint32_t)msk);
+      else
+        h.offb[q] = __builtin_bit_cast(double, (int64_t)(col * TPI) & msk);
       h.valb[q] = static_cast<double>(ld_s(a.vals + idc)) * okf;
     }
   };
@@ -939,9 +961,14 @@ __global__ ECG_SPMM_ATTR void k_spmm(SpArgs<S, SA> a) {
     static_for<kChunk>([&](auto jc) {
       constexpr int j = decltype(jc)::value;
       for (int q = 0; q < RPL; ++q) {
-        const int64_t off = __builtin_bit_cast(int64_t, bcast64<j>(h.offb[q]));
         const double vj = bcast64<j>(h.valb[q]);
-        const S* zr = a.Z + off + m;
+        const S* zr;
+        if constexpr (OFF32) {
+          const uint32_t off = (uint32_t)bcast32<j>(h.offw[q]) + (uint32_t)(m * sizeof(S));
+          zr = (const S*)((const char*)a.Z + (size_t)off);
+        } else {
+          zr = a.Z + __builtin_bit_cast(int64_t, bcast64<j>(h.offb[q])) + m;
+        }
         for (int e = 0; e < EPL; ++e) y[q][e] = __builtin_fma(vj, ld(zr + 16 * e), y[q][e]);
       }
     });
@@ -1031,6 +1058,239 @@ __global__ ECG_SPMM_ATTR void k_spmm(SpArgs<S, SA> a) {
       av[i] += __shfl_xor(av[i], 32, 64);
     }
     for (int w = 0; w < C::NWAVE; ++w) {
+      if (wave == w) {
+        for (int i = 0; i < EPL; ++i)
+          for (int j = 0; j < EPL; ++j)
+            for (int v = 0; v < 4; ++v) {
+              const int idx = (16 * i + 4 * v + rq) * TPI + 16 * j + m;
+              const bool first = (w == 0);
+              lds[idx] = (first ? 0.0 : lds[idx]) + accG[i][j][v];
+              lds[T2 + idx] = (first ? 0.0 : lds[T2 + idx]) + accF[i][j][v];
+              lds[2 * T2 + idx] = (first ? 0.0 : lds[2 * T2 + idx]) + accE[i][j][v];
+            }
+        if (rq == 0)
+          for (int i = 0; i < EPL; ++i) {
+            const int idx = 3 * T2 + 16 * i + m;
+            lds[idx] = (w == 0 ? 0.0 : lds[idx]) + av[i];
+          }
+      }
+      __syncthreads();
+    }
+    write_partial(lds, L, a.rc);
+  }
+}
+
+// Deeper pipeline for the product kernel: while step i is summed, the
+// gathers of step i+1, the first chunk of step i+2 and the row pointers of
+// step i+3 are in flight, so two steps of gathered rows are outstanding per
+// wave.  Every stage keeps two buffers indexed by the step's parity and the
+// loop is unrolled by two, so that no loaded register is copied (a copy
+// would wait for the load); loaded values stay raw until the step that
+// uses them for the same reason.
+template <int TPI, typename S, typename SA, bool GRAMS, bool HAS_PREV>
+__global__ ECG_SPMM_ATTR void k_spmm_deep(SpArgs<S, SA> a) {
+  constexpr int EPL = TPI / 16, RPL = ECG_SP_DRPL, T2 = TPI * TPI;
+  constexpr int WROWS = 4 * RPL, NWAVE = kThreads / 64, WGROWS = WROWS * NWAVE;
+  constexpr int L = 3 * T2 + TPI;
+  constexpr int LDSN = GRAMS ? L : 1;
+  __shared__ double lds[LDSN];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = lane & 15, rq = lane >> 4;
+
+  d4 accG[EPL][EPL], accF[EPL][EPL], accE[EPL][EPL];
+  double av[EPL];
+  for (int i = 0; i < EPL; ++i) {
+    av[i] = 0.0;
+    for (int j = 0; j < EPL; ++j) {
+      accG[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accF[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accE[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  }
+  const int64_t n = a.n;
+  const int nnz_last = a.rowptr[n] - 1;
+  const Steps sp = my_steps((n + WGROWS - 1) / WGROWS);
+
+  struct RowPtr {
+    int p0[RPL], p1[RPL];
+  };
+  struct Head {              // first chunk of a step and the step's row pointers
+    int col[RPL];
+    SA val[RPL];
+    int p0[RPL], p1[RPL];
+  };
+  struct Gath {
+    double v[kChunk][RPL][EPL];
+  };
+  struct Ops {
+    double z[RPL][EPL], pz[RPL][EPL], rv[RPL];
+  };
+  auto row_of = [&](int64_t step, int q) { return step * WGROWS + wave * WROWS + rq + 4 * q; };
+  auto load_rowptr = [&](int64_t step, RowPtr& rp) {
+    for (int q = 0; q < RPL; ++q) {
+      const int64_t row = row_of(step, q);
+      const int64_t rc = row < n ? row : n - 1;
+      rp.p0[q] = ld_s(a.rowptr + rc);
+      rp.p1[q] = ld_s(a.rowptr + rc + 1);
+    }
+  };
+  auto load_head = [&](const RowPtr& rp, Head& h) {
+    for (int q = 0; q < RPL; ++q) {
+      h.p0[q] = rp.p0[q];
+      h.p1[q] = rp.p1[q];
+      const int idc = min(rp.p0[q] + (m % kChunk), nnz_last);
+      h.col[q] = ld_s(a.colind + idc);
+      h.val[q] = ld_s(a.vals + idc);
+    }
+  };
+  // chunk c of step h: offsets and values with entries past the row masked
+  auto chunk_ov = [&](const Head& h, int c, const int (&col)[RPL], const SA (&val)[RPL],
+                      double (&offb)[RPL], double (&valb)[RPL]) {
+    for (int q = 0; q < RPL; ++q) {
+      const bool ok = h.p0[q] + c + (m % kChunk) < h.p1[q];
+      const int64_t msk = opaque((int64_t)(ok ? -1 : 0));
+      offb[q] = __builtin_bit_cast(double, ((int64_t)col[q] * TPI) & msk);
+      valb[q] = static_cast<double>(val[q]) * opaque(ok ? 1.0 : 0.0);
+    }
+  };
+  auto issue_gather = [&](const double (&offb)[RPL], Gath& g) {
+    static_for<kChunk>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      for (int q = 0; q < RPL; ++q) {
+        const int64_t off = __builtin_bit_cast(int64_t, bcast64<j>(offb[q]));
+        for (int e = 0; e < EPL; ++e) g.v[j][q][e] = ld(a.Z + off + m + 16 * e);
+      }
+    });
+  };
+  auto consume = [&](const double (&valb)[RPL], const Gath& g, double (&y)[RPL][EPL]) {
+    static_for<kChunk>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      for (int q = 0; q < RPL; ++q) {
+        const double vj = bcast64<j>(valb[q]);
+        for (int e = 0; e < EPL; ++e) y[q][e] = __builtin_fma(vj, g.v[j][q][e], y[q][e]);
+      }
+    });
+  };
+  auto load_ops = [&](int64_t step, Ops& o) {
+    if constexpr (GRAMS) {
+      for (int q = 0; q < RPL; ++q) {
+        const int64_t row = row_of(step, q);
+        const int64_t rc = row < n ? row : n - 1;
+        o.rv[q] = ld_s(a.rvec + rc);
+        for (int e = 0; e < EPL; ++e) {
+          o.z[q][e] = ld(a.Z + rc * TPI + m + 16 * e);
+          if constexpr (HAS_PREV)
+            o.pz[q][e] = static_cast<double>(ld_s(a.AZprev + rc * TPI + m + 16 * e));
+          else
+            o.pz[q][e] = 0.0;
+        }
+      }
+    }
+  };
+
+  const int64_t S0 = sp.first, SD = sp.stride, SE = sp.end;
+  RowPtr rp[2];
+  Head hd[2];
+  Gath g[2];
+  Ops o[2];
+  // Steps past the end are loaded like the others (their rows are clamped
+  // to n-1 and never stored): conditional loads would make the wait after
+  // the join cover every outstanding load.
+  // Order within the body of step i: (a) values of step i from its head;
+  // (b) row pointers of step i+3 and the head of step i+2 (addresses known
+  // from loads of the previous body that precede its gathers); (c) gathers
+  // of step i+1; (d) sum of step i, whose wait leaves (b) and (c) in flight.
+  // prologue: heads of steps 0 and 1, row pointers of step 2, gathers of step 0
+  if (S0 < SE) {
+    load_rowptr(S0, rp[0]);
+    load_rowptr(S0 + SD, rp[1]);
+    load_head(rp[0], hd[0]);
+    load_head(rp[1], hd[1]);
+    load_rowptr(S0 + 2 * SD, rp[0]);
+    double offb[RPL], valb[RPL];
+    chunk_ov(hd[0], 0, hd[0].col, hd[0].val, offb, valb);
+    issue_gather(offb, g[0]);
+    load_ops(S0, o[0]);
+  }
+  // one step with the buffers of parity P (step i) and 1-P (step i+1)
+  auto body = [&](auto pc, int64_t step) {
+    constexpr int P = decltype(pc)::value, Q = 1 - P;
+    // (a) step i's values from its head, which is then free
+    double valb_i[RPL];
+    int p0_i[RPL], p1_i[RPL];
+    {
+      double offb[RPL];
+      chunk_ov(hd[P], 0, hd[P].col, hd[P].val, offb, valb_i);
+      for (int q = 0; q < RPL; ++q) {
+        p0_i[q] = hd[P].p0[q];
+        p1_i[q] = hd[P].p1[q];
+      }
+    }
+    // (b) head of step i+2 (row pointers in rp[P]), row pointers of step i+3
+    load_head(rp[P], hd[P]);
+    load_rowptr(step + 3 * SD, rp[Q]);
+    // (c) gathers and Gram operands of step i+1
+    {
+      double offb[RPL], valb[RPL];
+      chunk_ov(hd[Q], 0, hd[Q].col, hd[Q].val, offb, valb);
+      issue_gather(offb, g[Q]);
+      load_ops(step + SD, o[Q]);
+    }
+    // (d) step i
+    double y[RPL][EPL];
+    for (int q = 0; q < RPL; ++q)
+      for (int e = 0; e < EPL; ++e) y[q][e] = 0.0;
+    consume(valb_i, g[P], y);
+    int len = 0;
+    for (int q = 0; q < RPL; ++q) len = max(len, p1_i[q] - p0_i[q]);
+    for (int c = kChunk; c < len; c += kChunk) {   // rows longer than one chunk
+      Head hx;
+      for (int q = 0; q < RPL; ++q) {
+        hx.p0[q] = p0_i[q];
+        hx.p1[q] = p1_i[q];
+        const int idc = min(p0_i[q] + c + (m % kChunk), nnz_last);
+        hx.col[q] = ld_s(a.colind + idc);
+        hx.val[q] = ld_s(a.vals + idc);
+      }
+      double offb[RPL], valb[RPL];
+      chunk_ov(hx, c, hx.col, hx.val, offb, valb);
+      Gath gx;
+      issue_gather(offb, gx);
+      consume(valb, gx, y);
+    }
+    double okf[RPL];
+    for (int q = 0; q < RPL; ++q) {
+      const int64_t row = row_of(step, q);
+      okf[q] = opaque(row < n ? 1.0 : 0.0);
+      if (row < n)
+        for (int e = 0; e < EPL; ++e) st_s(a.AZ + row * TPI + m + 16 * e, static_cast<S>(y[q][e]));
+    }
+    if constexpr (GRAMS) {
+      for (int q = 0; q < RPL; ++q) {
+        // y is zero on rows past the end, which masks every Gram; a = Z^t r
+        // takes the mask itself
+        for (int e = 0; e < EPL; ++e) y[q][e] = static_cast<double>(static_cast<S>(y[q][e])) * okf[q];
+        for (int i = 0; i < EPL; ++i) {
+          av[i] = __builtin_fma(o[P].z[q][i] * okf[q], o[P].rv[q], av[i]);
+          for (int j = 0; j < EPL; ++j) {
+            accG[i][j] = mfma16(o[P].z[q][i], y[q][j], accG[i][j]);
+            accF[i][j] = mfma16(y[q][i], y[q][j], accF[i][j]);
+            if constexpr (HAS_PREV) accE[i][j] = mfma16(o[P].pz[q][i], y[q][j], accE[i][j]);
+          }
+        }
+      }
+    }
+  };
+  for (int64_t step = S0; step < SE; step += 2 * SD) {
+    body(std::integral_constant<int, 0>{}, step);
+    if (step + SD < SE) body(std::integral_constant<int, 1>{}, step + SD);
+  }
+  if constexpr (GRAMS) {
+    for (int i = 0; i < EPL; ++i) {
+      av[i] += __shfl_xor(av[i], 16, 64);
+      av[i] += __shfl_xor(av[i], 32, 64);
+    }
+    for (int w = 0; w < NWAVE; ++w) {
       if (wave == w) {
         for (int i = 0; i < EPL; ++i)
           for (int j = 0; j < EPL; ++j)
@@ -1701,18 +1961,32 @@ hipError_t launch_spmm(bool grams, bool has_prev, int tail, const SpArgs<S, SA>&
       hipLaunchKernelGGL((k_spmm_cs<TPI, S, SA, true, false>), dim3(grid), blk, 0, st, a);
     return hipGetLastError();
   }
+  if constexpr (TPI == 16 && (ECG_SP_DEEP == 2 || (ECG_SP_DEEP == 1 && sizeof(S) == 4))) {
+    if (grams && tail != TAIL_SPMM) return hipErrorInvalidValue;
+    if (!grams)
+      hipLaunchKernelGGL((k_spmm_deep<TPI, S, SA, false, false>), dim3(grid), dim3(kThreads), 0, st, a);
+    else if (has_prev)
+      hipLaunchKernelGGL((k_spmm_deep<TPI, S, SA, true, true>), dim3(grid), dim3(kThreads), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_spmm_deep<TPI, S, SA, true, false>), dim3(grid), dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+  }
+  const bool off32 = ECG_SP_OFF32 != 0 && (uint64_t)a.n * TPI * sizeof(S) < (1ull << 32);
+#define ECG_SPL(G, H, T)                                                                    \
+  if (off32)                                                                                \
+    hipLaunchKernelGGL((k_spmm<TPI, S, SA, G, H, T, true>), dim3(grid), dim3(kThreads), 0, st, a); \
+  else                                                                                      \
+    hipLaunchKernelGGL((k_spmm<TPI, S, SA, G, H, T, false>), dim3(grid), dim3(kThreads), 0, st, a);
   if (!grams) {
-    hipLaunchKernelGGL((k_spmm<TPI, S, SA, false, false, TAIL_NONE>), dim3(grid), dim3(kThreads),
-                       0, st, a);
+    ECG_SPL(false, false, TAIL_NONE)
   } else if (tail != TAIL_SPMM) {
     return hipErrorInvalidValue;
   } else if (has_prev) {
-    hipLaunchKernelGGL((k_spmm<TPI, S, SA, true, true, TAIL_SPMM>), dim3(grid), dim3(kThreads),
-                       0, st, a);
+    ECG_SPL(true, true, TAIL_SPMM)
   } else {
-    hipLaunchKernelGGL((k_spmm<TPI, S, SA, true, false, TAIL_SPMM>), dim3(grid), dim3(kThreads),
-                       0, st, a);
+    ECG_SPL(true, false, TAIL_SPMM)
   }
+#undef ECG_SPL
   return hipGetLastError();
 }
 
