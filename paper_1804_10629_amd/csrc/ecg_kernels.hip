@@ -158,6 +158,9 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #ifndef ECG_SP_OFF32
 #define ECG_SP_OFF32 0         // 32-bit gather offsets when the block spans < 4 GiB
 #endif
+#ifndef ECG_SP_WIDE
+#define ECG_SP_WIDE 1          // wide-gather product kernel for 16-column binary64 blocks
+#endif
 #ifndef ECG_SP_DEEP
 #define ECG_SP_DEEP 1          // deeper-pipelined product kernel at 16 columns: 1 for
                                // binary32 blocks (faster there), 2 always, 0 never
@@ -1080,6 +1083,182 @@ __global__ ECG_SPMM_ATTR void k_spmm(SpArgs<S, SA> a) {
   }
 }
 
+// Wide-gather product kernel for 16-column binary64 blocks.  The gathers
+// dominate the kernel's vector-memory instructions and its address unit is
+// the busy resource, so rows are gathered 16 bytes per lane: 8 lanes per
+// row (lane l: row l / 8 of an 8-row set, columns 2 (l % 8) and
+// 2 (l % 8) + 1), a (column, value) pair per lane (entry l % 8 of the row's
+// chunk), half the gather instructions of the 16-lanes-per-row form.  The
+// Gram epilogue needs 16 lanes per row (the MFMA operand layout): A Z is
+// moved there with ds_bpermute, Z and A Z_prev are loaded in it directly.
+// Pipeline: row pointers two steps ahead, the chunk one step ahead, loaded
+// values processed only in the step that uses them.
+__device__ __forceinline__ double bperm64(int src_lane, double v) {
+  const int lo = __builtin_amdgcn_ds_bpermute(src_lane * 4, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(src_lane * 4, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// Value of lane 8 * (lane / 8) + N (N < 8) of a 64-bit register: row
+// broadcasts of lanes N and N + 8, chosen by the lane's half row.
+template <int N>
+__device__ __forceinline__ double bcast8_64(double v, bool upper) {
+  const double a = bcast64<N>(v), b = bcast64<N + 8>(v);
+  return upper ? b : a;
+}
+template <int N>
+__device__ __forceinline__ int bcast8_32(int v, bool upper) {
+  const int a = bcast32<N>(v), b = bcast32<N + 8>(v);
+  return upper ? b : a;
+}
+
+template <bool GRAMS, bool HAS_PREV>
+__global__ ECG_SPMM_ATTR void k_spmm_wide(SpArgs<double, double> a) {
+  constexpr int TPI = 16, T2 = TPI * TPI, L = 3 * T2 + TPI;
+  constexpr int RQ = 2;                          // 8-row sets per wave step
+  constexpr int WROWS = 8 * RQ, NWAVE = kThreads / 64, WGROWS = WROWS * NWAVE;
+  constexpr int LDSN = GRAMS ? L : 1;
+  __shared__ double lds[LDSN];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ri = lane >> 3, pp = lane & 7;       // gather layout
+  const int m = lane & 15, rq = lane >> 4;       // MFMA layout
+  const bool upper = (lane & 8) != 0;
+
+  d4 accG = d4{0.0, 0.0, 0.0, 0.0}, accF = accG, accE = accG;
+  double av = 0.0;
+  const int64_t n = a.n;
+  const int nnz_last = a.rowptr[n] - 1;
+  const Steps sp = my_steps((n + WGROWS - 1) / WGROWS);
+
+  struct RowPtr {
+    int p0[RQ], p1[RQ];
+  };
+  struct Head {              // raw chunk: entry pp of each row set's row
+    int col[RQ];
+    double val[RQ];
+  };
+  auto row_of = [&](int64_t step, int q) { return step * WGROWS + wave * WROWS + ri + 8 * q; };
+  auto load_rowptr = [&](int64_t step, RowPtr& rp) {
+    for (int q = 0; q < RQ; ++q) {
+      const int64_t row = row_of(step, q);
+      const int64_t rc = row < n ? row : n - 1;
+      rp.p0[q] = ld_s(a.rowptr + rc);
+      rp.p1[q] = ld_s(a.rowptr + rc + 1);
+    }
+  };
+  auto load_chunk = [&](const RowPtr& rp, int c, Head& h) {
+    for (int q = 0; q < RQ; ++q) {
+      const int idc = min(rp.p0[q] + c + pp, nnz_last);
+      h.col[q] = ld_s(a.colind + idc);
+      h.val[q] = ld_s(a.vals + idc);
+    }
+  };
+  // sum of chunk c of the step's rows into y (two columns per lane)
+  auto gather = [&](const RowPtr& rp, int c, const Head& h, double (&y)[RQ][2]) {
+    int offw[RQ];
+    double valb[RQ];
+    for (int q = 0; q < RQ; ++q) {
+      const bool ok = rp.p0[q] + c + pp < rp.p1[q];
+      offw[q] = ok ? h.col[q] : 0;
+      valb[q] = h.val[q] * opaque(ok ? 1.0 : 0.0);
+    }
+    static_for<8>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      for (int q = 0; q < RQ; ++q) {
+        const int col = bcast8_32<j>(offw[q], upper);
+        const double vj = bcast8_64<j>(valb[q], upper);
+        const double2 z = *reinterpret_cast<const double2*>(a.Z + (int64_t)col * TPI + 2 * pp);
+        y[q][0] = __builtin_fma(vj, z.x, y[q][0]);
+        y[q][1] = __builtin_fma(vj, z.y, y[q][1]);
+      }
+    });
+  };
+
+  RowPtr rp_cur, rp_nxt;
+  Head h_cur;
+  int64_t step = sp.first;
+  if (step < sp.end) {
+    load_rowptr(step, rp_cur);
+    load_chunk(rp_cur, 0, h_cur);
+    load_rowptr(step + sp.stride, rp_nxt);   // rows past the end are clamped
+  }
+  for (; step < sp.end; step += sp.stride) {
+    // next step's chunk and the row pointers after it: issued before this
+    // step's gathers, processed only when used (no wait here)
+    Head h_nxt;
+    RowPtr rp_nn;
+    load_chunk(rp_nxt, 0, h_nxt);
+    load_rowptr(step + 2 * sp.stride, rp_nn);
+    // Gram operands in the MFMA layout (lane: row rq + 4 k, column m)
+    double z[4], pz[4], rv[4], okm[4];
+    if constexpr (GRAMS) {
+      for (int k = 0; k < 4; ++k) {
+        const int64_t row = step * WGROWS + wave * WROWS + rq + 4 * k;
+        const int64_t rc = row < n ? row : n - 1;
+        okm[k] = opaque(row < n ? 1.0 : 0.0);
+        rv[k] = ld_s(a.rvec + rc);
+        z[k] = a.Z[rc * TPI + m];
+        pz[k] = HAS_PREV ? ld_s(a.AZprev + rc * TPI + m) : 0.0;
+      }
+    }
+    double y[RQ][2];
+    for (int q = 0; q < RQ; ++q) y[q][0] = y[q][1] = 0.0;
+    gather(rp_cur, 0, h_cur, y);
+    int len = 0;
+    for (int q = 0; q < RQ; ++q) len = max(len, rp_cur.p1[q] - rp_cur.p0[q]);
+    for (int c = 8; c < len; c += 8) {   // rows longer than one chunk
+      Head h;
+      load_chunk(rp_cur, c, h);
+      gather(rp_cur, c, h, y);
+    }
+    for (int q = 0; q < RQ; ++q) {
+      const int64_t row = row_of(step, q);
+      if (row < n) {
+        double2 v;
+        v.x = y[q][0];
+        v.y = y[q][1];
+        *reinterpret_cast<double2*>(a.AZ + row * TPI + 2 * pp) = v;
+      }
+    }
+    if constexpr (GRAMS) {
+      // A Z into the MFMA layout: row 4 k + rq of the step (row set k / 2,
+      // row (4 k + rq) % 8 of it), column m (lane 8 ((4 k + rq) % 8) + m / 2,
+      // element m % 2)
+      for (int k = 0; k < 4; ++k) {
+        const int q = k >> 1;
+        const int src = 8 * (4 * (k & 1) + rq) + (m >> 1);
+        const double e0 = bperm64(src, y[q][0]), e1 = bperm64(src, y[q][1]);
+        const double yk = ((m & 1) ? e1 : e0) * okm[k];
+        av = __builtin_fma(z[k] * okm[k], rv[k], av);
+        accG = mfma16(z[k], yk, accG);
+        accF = mfma16(yk, yk, accF);
+        if constexpr (HAS_PREV) accE = mfma16(pz[k], yk, accE);
+      }
+    }
+    h_cur = h_nxt;
+    rp_cur = rp_nxt;
+    rp_nxt = rp_nn;
+  }
+  if constexpr (GRAMS) {
+    av += __shfl_xor(av, 16, 64);
+    av += __shfl_xor(av, 32, 64);
+    for (int w = 0; w < NWAVE; ++w) {
+      if (wave == w) {
+        for (int v = 0; v < 4; ++v) {
+          const int idx = (4 * v + rq) * TPI + m;
+          const bool first = (w == 0);
+          lds[idx] = (first ? 0.0 : lds[idx]) + accG[v];
+          lds[T2 + idx] = (first ? 0.0 : lds[T2 + idx]) + accF[v];
+          lds[2 * T2 + idx] = (first ? 0.0 : lds[2 * T2 + idx]) + accE[v];
+        }
+        if (rq == 0) lds[3 * T2 + m] = (w == 0 ? 0.0 : lds[3 * T2 + m]) + av;
+      }
+      __syncthreads();
+    }
+    write_partial(lds, L, a.rc);
+  }
+}
+
 // Deeper pipeline for the product kernel: while step i is summed, the
 // gathers of step i+1, the first chunk of step i+2 and the row pointers of
 // step i+3 are in flight, so two steps of gathered rows are outstanding per
@@ -1959,6 +2138,17 @@ hipError_t launch_spmm(bool grams, bool has_prev, int tail, const SpArgs<S, SA>&
       hipLaunchKernelGGL((k_spmm_cs<TPI, S, SA, true, true>), dim3(grid), blk, 0, st, a);
     else
       hipLaunchKernelGGL((k_spmm_cs<TPI, S, SA, true, false>), dim3(grid), blk, 0, st, a);
+    return hipGetLastError();
+  }
+  if constexpr (ECG_SP_WIDE != 0 && TPI == 16 && std::is_same<S, double>::value &&
+                std::is_same<SA, double>::value) {
+    if (grams && tail != TAIL_SPMM) return hipErrorInvalidValue;
+    if (!grams)
+      hipLaunchKernelGGL((k_spmm_wide<false, false>), dim3(grid), dim3(kThreads), 0, st, a);
+    else if (has_prev)
+      hipLaunchKernelGGL((k_spmm_wide<true, true>), dim3(grid), dim3(kThreads), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_spmm_wide<true, false>), dim3(grid), dim3(kThreads), 0, st, a);
     return hipGetLastError();
   }
   if constexpr (TPI == 16 && (ECG_SP_DEEP == 2 || (ECG_SP_DEEP == 1 && sizeof(S) == 4))) {
