@@ -161,6 +161,9 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #ifndef ECG_SP_WIDE
 #define ECG_SP_WIDE 1          // wide-gather product kernel for 16-column binary64 blocks
 #endif
+#ifndef ECG_SPWF_RQ
+#define ECG_SPWF_RQ 1          // 16-row sets per step of the binary32 wide-gather kernel
+#endif
 #ifndef ECG_SP_DEEP
 #define ECG_SP_DEEP 1          // deeper-pipelined product kernel at 16 columns: 1 for
                                // binary32 blocks (faster there), 2 always, 0 never
@@ -1259,6 +1262,173 @@ __global__ ECG_SPMM_ATTR void k_spmm_wide(SpArgs<double, double> a) {
   }
 }
 
+// The wide-gather form for 16-column binary32 blocks: a row is 64 bytes, so
+// 4 lanes per row gather 16 bytes each (columns 4 (l % 4) .. 4 (l % 4) + 3)
+// and each lane holds two entries (l % 4 and l % 4 + 4) of its row's chunk,
+// broadcast within the quad with quad_perm.  RQ sets of 16 rows per step.
+template <int N>
+__device__ __forceinline__ int qbcast32(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, N | (N << 2) | (N << 4) | (N << 6), 0xF, 0xF, false);
+}
+
+template <bool GRAMS, bool HAS_PREV>
+__global__ ECG_SPMM_ATTR void k_spmm_widef(SpArgs<float, float> a) {
+  constexpr int TPI = 16, T2 = TPI * TPI, L = 3 * T2 + TPI;
+  constexpr int RQ = ECG_SPWF_RQ;                // 16-row sets per wave step
+  constexpr int WROWS = 16 * RQ, NWAVE = kThreads / 64, WGROWS = WROWS * NWAVE;
+  constexpr int LDSN = GRAMS ? L : 1;
+  __shared__ double lds[LDSN];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ri = lane >> 2, pp = lane & 3;       // gather layout
+  const int m = lane & 15, rq = lane >> 4;       // MFMA layout
+
+  d4 accG = d4{0.0, 0.0, 0.0, 0.0}, accF = accG, accE = accG;
+  double av = 0.0;
+  const int64_t n = a.n;
+  const int nnz_last = a.rowptr[n] - 1;
+  const Steps sp = my_steps((n + WGROWS - 1) / WGROWS);
+
+  struct RowPtr {
+    int p0[RQ], p1[RQ];
+  };
+  struct Head {              // raw chunk: entries pp and pp + 4 of the row
+    int col[RQ][2];
+    float val[RQ][2];
+  };
+  auto row_of = [&](int64_t step, int q) { return step * WGROWS + wave * WROWS + ri + 16 * q; };
+  auto load_rowptr = [&](int64_t step, RowPtr& rp) {
+    for (int q = 0; q < RQ; ++q) {
+      const int64_t row = row_of(step, q);
+      const int64_t rc = row < n ? row : n - 1;
+      rp.p0[q] = ld_s(a.rowptr + rc);
+      rp.p1[q] = ld_s(a.rowptr + rc + 1);
+    }
+  };
+  auto load_chunk = [&](const RowPtr& rp, int c, Head& h) {
+    for (int q = 0; q < RQ; ++q)
+      for (int u = 0; u < 2; ++u) {
+        const int idc = min(rp.p0[q] + c + pp + 4 * u, nnz_last);
+        h.col[q][u] = ld_s(a.colind + idc);
+        h.val[q][u] = ld_s(a.vals + idc);
+      }
+  };
+  // products of binary32 values accumulated in binary64, rounded once
+  auto gather = [&](const RowPtr& rp, int c, const Head& h, double (&y)[RQ][4]) {
+    int offw[RQ][2];
+    float valb[RQ][2];
+    for (int q = 0; q < RQ; ++q)
+      for (int u = 0; u < 2; ++u) {
+        const bool ok = rp.p0[q] + c + pp + 4 * u < rp.p1[q];
+        offw[q][u] = ok ? h.col[q][u] : 0;
+        valb[q][u] = h.val[q][u] * opaque(ok ? 1.0f : 0.0f);
+      }
+    static_for<8>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      for (int q = 0; q < RQ; ++q) {
+        const int col = qbcast32<j % 4>(offw[q][j / 4]);
+        const float vj = __builtin_bit_cast(float, qbcast32<j % 4>(__builtin_bit_cast(int, valb[q][j / 4])));
+        const float4 z = *reinterpret_cast<const float4*>(a.Z + (int64_t)col * TPI + 4 * pp);
+        const double vd = vj;
+        y[q][0] = __builtin_fma(vd, (double)z.x, y[q][0]);
+        y[q][1] = __builtin_fma(vd, (double)z.y, y[q][1]);
+        y[q][2] = __builtin_fma(vd, (double)z.z, y[q][2]);
+        y[q][3] = __builtin_fma(vd, (double)z.w, y[q][3]);
+      }
+    });
+  };
+
+  RowPtr rp_cur, rp_nxt;
+  Head h_cur;
+  int64_t step = sp.first;
+  if (step < sp.end) {
+    load_rowptr(step, rp_cur);
+    load_chunk(rp_cur, 0, h_cur);
+    load_rowptr(step + sp.stride, rp_nxt);
+  }
+  for (; step < sp.end; step += sp.stride) {
+    Head h_nxt;
+    RowPtr rp_nn;
+    load_chunk(rp_nxt, 0, h_nxt);
+    load_rowptr(step + 2 * sp.stride, rp_nn);
+    constexpr int NK = 4 * RQ;                   // 4-row groups of the step
+    double z[NK], pz[NK], rv[NK], okm[NK];
+    if constexpr (GRAMS) {
+      for (int k = 0; k < NK; ++k) {
+        const int64_t row = step * WGROWS + wave * WROWS + rq + 4 * k;
+        const int64_t rc = row < n ? row : n - 1;
+        okm[k] = opaque(row < n ? 1.0 : 0.0);
+        rv[k] = ld_s(a.rvec + rc);
+        z[k] = static_cast<double>(a.Z[rc * TPI + m]);
+        pz[k] = HAS_PREV ? static_cast<double>(ld_s(a.AZprev + rc * TPI + m)) : 0.0;
+      }
+    }
+    double yd[RQ][4];
+    for (int q = 0; q < RQ; ++q) yd[q][0] = yd[q][1] = yd[q][2] = yd[q][3] = 0.0;
+    gather(rp_cur, 0, h_cur, yd);
+    int len = 0;
+    for (int q = 0; q < RQ; ++q) len = max(len, rp_cur.p1[q] - rp_cur.p0[q]);
+    for (int c = 8; c < len; c += 8) {
+      Head h;
+      load_chunk(rp_cur, c, h);
+      gather(rp_cur, c, h, yd);
+    }
+    float y[RQ][4];                              // the stored values
+    for (int q = 0; q < RQ; ++q)
+      for (int u = 0; u < 4; ++u) y[q][u] = static_cast<float>(yd[q][u]);
+    for (int q = 0; q < RQ; ++q) {
+      const int64_t row = row_of(step, q);
+      if (row < n) {
+        float4 v;
+        v.x = y[q][0];
+        v.y = y[q][1];
+        v.z = y[q][2];
+        v.w = y[q][3];
+        *reinterpret_cast<float4*>(a.AZ + row * TPI + 4 * pp) = v;
+      }
+    }
+    if constexpr (GRAMS) {
+      // A Z into the MFMA layout: step row 4 k + rq is row (4 k + rq) % 16 of
+      // set (4 k + rq) / 16; column m is element m % 4 of lane 4 row + m / 4
+      for (int k = 0; k < NK; ++k) {
+        const int r = 4 * k + rq;
+        const int q = r >> 4;          // uniform in k for rq < 4: (4 k) / 16
+        const int src = 4 * (r & 15) + (m >> 2);
+        float e[4];
+        for (int u = 0; u < 4; ++u)
+          e[u] = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src * 4, __builtin_bit_cast(int, y[k >> 2][u])));
+        (void)q;
+        const float ev = (m & 2) ? ((m & 1) ? e[3] : e[2]) : ((m & 1) ? e[1] : e[0]);
+        const double yk = static_cast<double>(ev) * okm[k];
+        av = __builtin_fma(z[k] * okm[k], rv[k], av);
+        accG = mfma16(z[k], yk, accG);
+        accF = mfma16(yk, yk, accF);
+        if constexpr (HAS_PREV) accE = mfma16(pz[k], yk, accE);
+      }
+    }
+    h_cur = h_nxt;
+    rp_cur = rp_nxt;
+    rp_nxt = rp_nn;
+  }
+  if constexpr (GRAMS) {
+    av += __shfl_xor(av, 16, 64);
+    av += __shfl_xor(av, 32, 64);
+    for (int w = 0; w < NWAVE; ++w) {
+      if (wave == w) {
+        for (int v = 0; v < 4; ++v) {
+          const int idx = (4 * v + rq) * TPI + m;
+          const bool first = (w == 0);
+          lds[idx] = (first ? 0.0 : lds[idx]) + accG[v];
+          lds[T2 + idx] = (first ? 0.0 : lds[T2 + idx]) + accF[v];
+          lds[2 * T2 + idx] = (first ? 0.0 : lds[2 * T2 + idx]) + accE[v];
+        }
+        if (rq == 0) lds[3 * T2 + m] = (w == 0 ? 0.0 : lds[3 * T2 + m]) + av;
+      }
+      __syncthreads();
+    }
+    write_partial(lds, L, a.rc);
+  }
+}
+
 // Deeper pipeline for the product kernel: while step i is summed, the
 // gathers of step i+1, the first chunk of step i+2 and the row pointers of
 // step i+3 are in flight, so two steps of gathered rows are outstanding per
@@ -2149,6 +2319,17 @@ hipError_t launch_spmm(bool grams, bool has_prev, int tail, const SpArgs<S, SA>&
       hipLaunchKernelGGL((k_spmm_wide<true, true>), dim3(grid), dim3(kThreads), 0, st, a);
     else
       hipLaunchKernelGGL((k_spmm_wide<true, false>), dim3(grid), dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+  }
+  if constexpr (ECG_SP_WIDE != 0 && TPI == 16 && std::is_same<S, float>::value &&
+                std::is_same<SA, float>::value) {
+    if (grams && tail != TAIL_SPMM) return hipErrorInvalidValue;
+    if (!grams)
+      hipLaunchKernelGGL((k_spmm_widef<false, false>), dim3(grid), dim3(kThreads), 0, st, a);
+    else if (has_prev)
+      hipLaunchKernelGGL((k_spmm_widef<true, true>), dim3(grid), dim3(kThreads), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_spmm_widef<true, false>), dim3(grid), dim3(kThreads), 0, st, a);
     return hipGetLastError();
   }
   if constexpr (TPI == 16 && (ECG_SP_DEEP == 2 || (ECG_SP_DEEP == 1 && sizeof(S) == 4))) {
