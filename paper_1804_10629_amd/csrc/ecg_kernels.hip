@@ -161,6 +161,12 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #ifndef ECG_SP_WIDE
 #define ECG_SP_WIDE 1          // wide-gather product kernel for 16-column binary64 blocks
 #endif
+#ifndef ECG_XR_WIDE
+#define ECG_XR_WIDE 1          // 16-byte-load x/r update for one 16-column block
+#endif
+#ifndef ECG_XR_RQ
+#define ECG_XR_RQ 4            // row sets per step of that kernel
+#endif
 #ifndef ECG_SPWF_RQ
 #define ECG_SPWF_RQ 1          // 16-row sets per step of the binary32 wide-gather kernel
 #endif
@@ -322,10 +328,12 @@ __device__ void w_chol(double (&g)[TPI], int t, int* bad) {
     const double d = sqrt(d2);
     const double rj = c > j ? g[j] / d : (c == j ? d : 0.0);
     const double rjc = c < t ? rj : 0.0;
-    // trailing update of the rows below j: G[i][c] -= R[j][i] R[j][c]
+    // trailing update of the rows below j: G[i][c] -= R[j][i] R[j][c],
+    // R[j][i] broadcast from lane i by the FMA's DPP operand
+    const double nrjc = -rjc;
     static_for<TPI - j - 1>([&](auto ic) {
       constexpr int i = j + 1 + decltype(ic)::value;
-      g[i] = __builtin_fma(-lane_value<i>(rjc), rjc, g[i]);
+      g[i] = ic == 0 ? fmac_bcast<i, true>(g[i], rjc, nrjc) : fmac_bcast<i, false>(g[i], rjc, nrjc);
     });
     g[j] = rjc;              // R[j][c]; zero for j > c
   });
@@ -368,7 +376,9 @@ __device__ void tail_spmm(double* sums, double* tmp, const TailArgs& ta) {
   const double* a = sums + 3 * T2;
   double* Rp = tmp + 2 * TPI;
   const bool prev = ta.m >= 2 && ta.rinv_p1 != nullptr;
-  if (prev) mat_to_lds<TPI>(ta.rinv_p1, Rp, c);
+  // R_{m-1}^{-1} is read from global memory while the factorisation runs
+  double rp[TPI];
+  if (prev) col_load<TPI>(ta.rinv_p1, c, rp);
   int bad = 0;
   double x[TPI], y[TPI], h[TPI];
   col_load<TPI>(G, c, x);
@@ -377,6 +387,7 @@ __device__ void tail_spmm(double* sums, double* tmp, const TailArgs& ta) {
   col_store<TPI>(G, c, x, 1.0);               // G <- R
   wsync();
   w_trinv<TPI>(G, t, y);                      // y: column c of R^{-1}
+  if (prev) col_store<TPI>(Rp, c, rp, 1.0);
   wsync();
   col_store<TPI>(G, c, y, 1.0);               // G <- R^{-1}
   col_store<TPI>(ta.rinv_cur, c, y, 1.0);
@@ -416,8 +427,10 @@ template <int TPI>
 __device__ void tail_cgs(double* sums, double* tmp, int ng, const TailArgs& ta) {
   constexpr int T2 = TPI * TPI;
   const int c = threadIdx.x & 63;
+  double rg[2][TPI];                          // both R^{-1} in flight at once
+  for (int g = 0; g < ng; ++g) col_load<TPI>(g == 0 ? ta.rinv_p1 : ta.rinv_p2, c, rg[g]);
   for (int g = 0; g < ng; ++g) {
-    mat_to_lds<TPI>(g == 0 ? ta.rinv_p1 : ta.rinv_p2, tmp, c);
+    col_store<TPI>(tmp, c, rg[g], 1.0);
     double x[TPI], y[TPI];
     col_load<TPI>(sums + g * T2, c, x);
     wsync();
@@ -2051,6 +2064,74 @@ __global__ ECG_STREAM void k_xr(XRArgs<S> a) {
   write_partial(red, 1, a.rc);
 }
 
+// One block at 16 columns (the x/r update that ends an s-step iteration):
+// 16-byte loads, LPR = 16 / (values per 16 bytes) lanes per row, so a wave
+// instruction covers 8 (binary64) or 16 (binary32) rows; RQ such row sets
+// per step.  Row sums over a row's lanes by DPP; the row's first lane
+// writes x and r.
+template <typename S>
+__global__ ECG_STREAM void k_xr_wide(XRArgs<S> a) {
+  constexpr int TPI = 16, VPL = 16 / sizeof(S), LPR = TPI / VPL;
+  constexpr int RSET = 64 / LPR, RQ = ECG_XR_RQ;
+  constexpr int WROWS = RSET * RQ, NWAVE = kThreads / 64, WGROWS = WROWS * NWAVE;
+  using V = typename std::conditional<sizeof(S) == 8, double2, float4>::type;
+  __shared__ double bl[TPI];
+  __shared__ double red[8];
+  if (a.status_in->breakdown) return;     // uniform: the host stops after this iteration
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ri = lane / LPR, pp = lane % LPR;
+  if (tid < TPI) bl[tid] = a.beta[0][tid];
+  __syncthreads();
+  double bv[VPL];
+  for (int u = 0; u < VPL; ++u) bv[u] = bl[VPL * pp + u];
+  double rr = 0.0;
+  const int64_t n = a.n;
+  const Steps sp = my_steps((n + WGROWS - 1) / WGROWS);
+  for (int64_t step = sp.first; step < sp.end; step += sp.stride) {
+    const int64_t row0 = step * WGROWS + wave * WROWS + ri;
+    int64_t rowc[RQ];
+    V u[RQ], au[RQ];
+    double xo[RQ], ro[RQ];
+    for (int q = 0; q < RQ; ++q) {
+      const int64_t row = row0 + RSET * q;
+      rowc[q] = row < n ? row : n - 1;
+      u[q] = *reinterpret_cast<const V*>(a.U[0] + rowc[q] * TPI + VPL * pp);
+      au[q] = *reinterpret_cast<const V*>(a.AU[0] + rowc[q] * TPI + VPL * pp);
+      xo[q] = a.x_in[rowc[q]];
+      ro[q] = a.r_in[rowc[q]];
+    }
+    for (int q = 0; q < RQ; ++q) {
+      const S* uv = reinterpret_cast<const S*>(&u[q]);
+      const S* av = reinterpret_cast<const S*>(&au[q]);
+      double dx = 0.0, dr = 0.0;
+      for (int e = 0; e < VPL; ++e) {
+        dx = __builtin_fma(static_cast<double>(uv[e]), bv[e], dx);
+        dr = __builtin_fma(static_cast<double>(av[e]), bv[e], dr);
+      }
+      // sums over the LPR lanes of the row (pairs, quads, then eights)
+      dx += __builtin_amdgcn_update_dpp(dx, dx, 0xB1, 0xF, 0xF, false);
+      dr += __builtin_amdgcn_update_dpp(dr, dr, 0xB1, 0xF, 0xF, false);
+      dx += __builtin_amdgcn_update_dpp(dx, dx, 0x4E, 0xF, 0xF, false);
+      dr += __builtin_amdgcn_update_dpp(dr, dr, 0x4E, 0xF, 0xF, false);
+      if constexpr (LPR == 8) {
+        dx += __builtin_amdgcn_update_dpp(dx, dx, 0x141, 0xF, 0xF, false);
+        dr += __builtin_amdgcn_update_dpp(dr, dr, 0x141, 0xF, 0xF, false);
+      }
+      const int64_t row = row0 + RSET * q;
+      const double rn = ro[q] - dr;
+      if (pp == 0 && row < n) {
+        a.x[row] = xo[q] + dx;
+        a.r[row] = rn;
+        rr += rn * rn;
+      }
+    }
+  }
+  const double s = wg_sum(rr, red);
+  if (tid == 0) red[0] = s;
+  __syncthreads();
+  write_partial(red, 1, a.rc);
+}
+
 template <int TPI, typename S>
 __global__ void k_basis_export(const S* __restrict__ U, const double* __restrict__ rinv,
                                double* __restrict__ V, int64_t n, int t, int ldv, int col0) {
@@ -2363,7 +2444,9 @@ hipError_t launch_spmm(bool grams, bool has_prev, int tail, const SpArgs<S, SA>&
 
 template <int TPI, typename S>
 hipError_t launch_xr(const XRArgs<S>& a, int grid, hipStream_t st) {
-  if (a.nb == 1)
+  if (ECG_XR_WIDE && TPI == 16 && a.nb == 1)
+    hipLaunchKernelGGL((k_xr_wide<S>), dim3(grid), dim3(kThreads), 0, st, a);
+  else if (a.nb == 1)
     hipLaunchKernelGGL((k_xr<TPI, S, 1>), dim3(grid), dim3(kThreads), 0, st, a);
   else
     hipLaunchKernelGGL((k_xr<TPI, S, 4>), dim3(grid), dim3(kThreads), 0, st, a);
