@@ -75,7 +75,7 @@ typedef struct ecg_opts {
   int32_t device_ptrs;    /* 0: host arrays, 1: device arrays (default 0) */
   double  inner_tol;      /* ECG_MIXED: restart from the true residual when the
                              recursive residual is <= inner_tol times the one
-                             at the last restart (default 1e-5; ignored in
+                             at the last restart (default 1e-4; ignored in
                              ECG_FP64) */
   int32_t max_restarts;   /* bound on residual replacements (default 20) */
   int32_t q_cap_blocks;   /* ECG_SRECG2, ECG_MSDO: blocks kept since the last

@@ -200,7 +200,7 @@ class Solver:
 
     def __init__(self, rowptr, colind, vals, partition, t: int, s: int, *,
                  variant: int = SRECG, orth: int = ACHOLQR, precision: int = FP64,
-                 inner_tol: float = 1e-5, max_restarts: int = 20, q_cap_blocks: int = 0,
+                 inner_tol: float = 1e-4, max_restarts: int = 20, q_cap_blocks: int = 0,
                  ws_cap_bytes: int = 0, collect_stats: bool = False, grid: int = 0):
         torch = _torch()
         self._ctx = _P()

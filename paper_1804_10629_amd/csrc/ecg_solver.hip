@@ -165,7 +165,7 @@ void ecg_opts_default(ecg_opts* o) {
   o->orth = ECG_ACHOLQR;
   o->precision = ECG_FP64;
   o->device_ptrs = 0;
-  o->inner_tol = 1e-5;
+  o->inner_tol = 1e-4;
   o->max_restarts = 20;
   o->q_cap_blocks = 0;
   o->ws_cap_bytes = 0;

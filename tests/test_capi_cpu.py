@@ -44,7 +44,7 @@ def test_opts_default():
     o = E._Opts()
     E.lib.ecg_opts_default(ctypes.byref(o))
     assert (o.variant, o.orth, o.precision, o.device_ptrs) == (0, 0, 0, 0)
-    assert o.inner_tol == 1e-5 and o.max_restarts == 20 and o.grid == 0
+    assert o.inner_tol == 1e-4 and o.max_restarts == 20 and o.grid == 0
     assert list(o.reserved) == [0] * 6
 
 

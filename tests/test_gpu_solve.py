@@ -187,7 +187,7 @@ def test_mixed_precision_reaches_tolerance(E, c1):
     # error against the FP64 oracle: both solutions satisfy the 1e-8
     # residual, so they agree to about cond(A) * 1e-8
     assert _rel(x, ref.x) <= 1e-5
-    m32 = O.sstep_srecg(A, dom, 8, 2, p.b, tol=1e-8, basis_dtype=np.float32, inner_tol=1e-5)
+    m32 = O.sstep_srecg(A, dom, 8, 2, p.b, tol=1e-8, basis_dtype=np.float32, inner_tol=1e-4)
     assert abs(info.iters - m32.iters) <= max(3, 0.1 * m32.iters)
 
 
