@@ -13,9 +13,11 @@ constexpr int kThreads = 256;     // threads per work-group of the block kernels
 constexpr int kMaxS = 16;         // largest s supported by the x/r update
 
 // Blocks of at least ECG_CS_MIN_TPI stored columns (64: at 32 the
-// row-per-lane-group kernels are faster) use the column-split
-// kernels: work-groups of cs_threads(TPI) threads in kCSGroups row groups,
-// each row group writing its own Gram partial.
+// row-per-lane-group kernels are faster) use the column-split product
+// kernel (work-groups of cs_threads(TPI) threads in kCSGroups row groups,
+// each row group writing its own Gram partial) and the matrix-core block
+// update (kCSGroups times as many work-groups of four waves, one partial
+// each), so both write gram_partials(TPI, grid) partials.
 #ifndef ECG_CS_MIN_TPI
 #define ECG_CS_MIN_TPI 64
 #endif

@@ -161,6 +161,9 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #ifndef ECG_SP_WIDE
 #define ECG_SP_WIDE 1          // wide-gather product kernel for 16-column binary64 blocks
 #endif
+#ifndef ECG_MF_WPE
+#define ECG_MF_WPE 2
+#endif
 #ifndef ECG_XR_WIDE
 #define ECG_XR_WIDE 1          // 16-byte-load x/r update for one 16-column block
 #endif
@@ -179,9 +182,6 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #endif
 #ifndef ECG_CS_RPL
 #define ECG_CS_RPL 2           // row quads per lane of the column-split kernels
-#endif
-#ifndef ECG_CS_CHAINS
-#define ECG_CS_CHAINS 4        // accumulation chains per output of the column-split update
 #endif
 #ifndef ECG_CS_WPE
 #define ECG_CS_WPE 2
@@ -1706,134 +1706,120 @@ __device__ __forceinline__ double pick(const double (&v)[EPL], int cb) {
   return r;
 }
 
-template <int TPI, typename S, int NU, int NG, bool IDENT0, bool WRITE, bool P0X>
-__global__ __launch_bounds__(cs_threads(TPI)) __attribute__((amdgpu_waves_per_eu(ECG_CS_WPE, ECG_CS_WPE)))
-void k_update_gram_cs(UGArgs<S> a) {
-  using C = CsCfg<TPI>;
-  constexpr int EPL = C::EPL, RPL = C::RPL, T2 = C::T2;
+// Block update and Grams at 64 columns on the matrix cores.  A work-group
+// of four waves takes 16 rows per step; wave w owns output columns
+// 16 w .. 16 w + 15.  The update out = sum_b X_b C_b is a 16 x 64 by 64 x 16
+// product per wave and operand: MFMA f64 16x16x4 with the rows as M, the
+// input columns as K (four per instruction) and the wave's output columns
+// as N.  The B operands (this wave's slice of each coefficient matrix) stay
+// in registers for the whole launch; the A operands (row l % 16, column
+// 4 kk + l / 16 of X_b) come from an LDS tile the four waves fill with
+// their column slices.  The result lands in the natural layout (lane: row
+// 4 v + l / 16, column l % 16), which is the B operand of the Gram products
+// H_g = P_g^t out (K = rows) and the layout of the coalesced store.
+template <typename S, int NU, int NG, bool IDENT0, bool WRITE, bool P0X>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ECG_MF_WPE, ECG_MF_WPE)))
+void k_update_gram_mf(UGArgs<S> a) {
+  constexpr int TPI = 64, T2 = TPI * TPI, LD = TPI + 1;   // LD: padded tile rows
   constexpr int NCOEF = NU - (IDENT0 ? 1 : 0);
   constexpr int NX = NU;
   constexpr int NP = NG - (P0X ? 1 : 0);
   constexpr int NLD = NX + NP;
-  constexpr int LDSN = NCOEF * T2 > 0 ? NCOEF * T2 : 1;
-  __shared__ double lds[LDSN];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m = lane & 15, rq = lane >> 4;
-  const int cb = wave % EPL, rg = wave / EPL;
-
-  for (int b = 0; b < NCOEF; ++b) {
-    const double* src = a.C[b + (IDENT0 ? 1 : 0)];
-    for (int idx = tid; idx < T2; idx += blockDim.x) lds[b * T2 + idx] = src[idx];
-  }
+  __shared__ double tile[NLD][16 * LD];
   __shared__ double fbeta[TPI];
+  const int tid = threadIdx.x, lane = tid & 63, cb = tid >> 6;
+  const int m = lane & 15, rq = lane >> 4;
+
+  // B operands: cf[b][kk] = C[4 kk + l / 16][16 cb + l % 16]
+  double cf[NCOEF > 0 ? NCOEF : 1][16];
+  for (int b = 0; b < NCOEF; ++b) {
+    const double* cm = a.C[b + (IDENT0 ? 1 : 0)];
+    for (int kk = 0; kk < 16; ++kk) cf[b][kk] = cm[(4 * kk + rq) * TPI + 16 * cb + m];
+  }
   const bool fold = !IDENT0 && NU >= 2 && a.fold_beta != nullptr && a.status->breakdown == 0;
   if (fold)
     for (int idx = tid; idx < TPI; idx += blockDim.x) fbeta[idx] = a.fold_beta[idx];
-  __syncthreads();
 
-  d4 acc[NG > 0 ? NG : 1][EPL];
+  d4 acc[NG > 0 ? NG : 1][4];
   for (int g = 0; g < (NG > 0 ? NG : 1); ++g)
-    for (int i = 0; i < EPL; ++i) acc[g][i] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int e = 0; e < 4; ++e) acc[g][e] = d4{0.0, 0.0, 0.0, 0.0};
 
   const S* src[NLD];
   for (int b = 0; b < NX; ++b) src[b] = a.X[b];
   for (int g = 0; g < NP; ++g) src[NX + g] = a.P[g + (P0X ? 1 : 0)];
 
   const int64_t n = a.n;
-  const Steps sp = my_steps((n + C::WGROWS - 1) / C::WGROWS);
+  const Steps sp = my_steps((n + 15) / 16);
   for (int64_t step = sp.first; step < sp.end; step += sp.stride) {
-    const int64_t row0 = step * C::WGROWS + rg * C::WROWS + rq;
-    double cur[NLD][RPL][EPL];
-    for (int q = 0; q < RPL; ++q) {
-      const int64_t row = row0 + 4 * q;
+    const int64_t row0 = step * 16 + rq;
+    // this wave's column slice of every operand, natural layout
+    double cur[NLD][4];
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = row0 + 4 * v;
       const int64_t rc = row < n ? row : n - 1;
       const double okf = opaque(row < n ? 1.0 : 0.0);
-      for (int b = 0; b < NLD; ++b)
-        for (int e = 0; e < EPL; ++e) cur[b][q][e] = ld(src[b] + rc * TPI + m + 16 * e) * okf;
+      for (int b = 0; b < NLD; ++b) cur[b][v] = ld(src[b] + rc * TPI + 16 * cb + m) * okf;
     }
-    if constexpr (!IDENT0 && NU >= 2) {
-      // every wave of the row group holds the full rows; column block 0 folds
-      if (fold && cb == 0) {
-        double xo[RPL], ro[RPL];
-        for (int q = 0; q < RPL; ++q) {
-          const int64_t row = row0 + 4 * q;
-          const int64_t rc = row < n ? row : n - 1;
-          xo[q] = a.x_in[rc];
-          ro[q] = a.r_in[rc];
-        }
-        for (int q = 0; q < RPL; ++q) {
-          double dx = 0.0, dr = 0.0;
-          for (int e = 0; e < EPL; ++e) {
-            const double bv = fbeta[m + 16 * e];
-            dx = __builtin_fma(cur[1][q][e], bv, dx);
-            dr = __builtin_fma(cur[0][q][e], bv, dr);
-          }
-          dx = row_sum16(dx);
-          dr = row_sum16(dr);
-          const int64_t row = row0 + 4 * q;
-          if (m == 0 && row < n) {
-            a.x_out[row] = xo[q] + dx;
-            a.r_out[row] = ro[q] - dr;
-          }
-        }
-      }
-    }
-    // NCH independent accumulation chains per row (the k-blocks of all
-    // coefficient matrices in turn): one chain would serialise NCOEF * TPI
-    // dependent FMAs per step
-    constexpr int NCH = ECG_CS_CHAINS;
-    double oc[NCH][RPL];
-    for (int h = 0; h < NCH; ++h)
-      for (int q = 0; q < RPL; ++q) oc[h][q] = (h == 0 && IDENT0) ? pick<EPL>(cur[0][q], cb) : 0.0;
-    constexpr int CG = ECG_UG_CGROUP;
+    __syncthreads();   // the previous step's tile readers are done (and fbeta is set)
+    for (int b = 0; b < NLD; ++b)
+      for (int v = 0; v < 4; ++v) tile[b][(4 * v + rq) * LD + 16 * cb + m] = cur[b][v];
+    __syncthreads();
+
+    d4 o;
+    for (int v = 0; v < 4; ++v) o[v] = IDENT0 ? cur[0][v] : 0.0;
     static_for<NCOEF>([&](auto bc) {
       constexpr int b = decltype(bc)::value;
       constexpr int xb = b + (IDENT0 ? 1 : 0);
-      static_for<EPL>([&](auto ec) {
-        constexpr int e2 = decltype(ec)::value;
-        constexpr int h = (b * EPL + e2) % NCH;
-        static_for<16 / CG>([&](auto gc) {
-          constexpr int g0 = CG * decltype(gc)::value;
-          asm volatile("" ::: "memory");
-          double cv[CG];
-          for (int u = 0; u < CG; ++u) cv[u] = lds[b * T2 + (16 * e2 + g0 + u) * TPI + 16 * cb + m];
-          static_for<CG>([&](auto uc) {
-            constexpr int u = decltype(uc)::value;
-            constexpr int nn = g0 + u;
-            for (int q = 0; q < RPL; ++q)
-              oc[h][q] = nn == 0 ? fmac_bcast<nn, true>(oc[h][q], cur[xb][q][e2], cv[u])
-                                 : fmac_bcast<nn, false>(oc[h][q], cur[xb][q][e2], cv[u]);
-          });
-        });
-      });
+      for (int kk = 0; kk < 16; ++kk) o = mfma16(tile[xb][m * LD + 4 * kk + rq], cf[b][kk], o);
     });
-    double o[RPL];
-    for (int q = 0; q < RPL; ++q) {
-      o[q] = oc[0][q];
-      for (int h = 1; h < NCH; ++h) o[q] += oc[h][q];
-    }
+
     if constexpr (WRITE) {
-      for (int q = 0; q < RPL; ++q) {
-        const int64_t row = row0 + 4 * q;
-        if (row < n) a.out[row * TPI + 16 * cb + m] = static_cast<S>(o[q]);
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = row0 + 4 * v;
+        if (row < n) a.out[row * TPI + 16 * cb + m] = static_cast<S>(o[v]);
       }
     }
     if constexpr (NG > 0) {
       static_for<NG>([&](auto gc) {
         constexpr int g = decltype(gc)::value;
         constexpr int slot = (P0X && g == 0) ? 0 : NX + g - (P0X ? 1 : 0);
-        for (int q = 0; q < RPL; ++q)
-          for (int i = 0; i < EPL; ++i) acc[g][i] = mfma16(cur[slot][q][i], o[q], acc[g][i]);
+        for (int e = 0; e < 4; ++e)
+          for (int v = 0; v < 4; ++v) {
+            const double pv = tile[slot][(4 * v + rq) * LD + 16 * e + m];
+            acc[g][e] = mfma16(pv, o[v], acc[g][e]);
+          }
       });
+    }
+    if constexpr (!IDENT0 && NU >= 2) {
+      // x/r contribution of the previous block (X[1] = U, X[0] = A U): wave 0
+      // reads the full rows from the tiles
+      if (fold && cb == 0) {
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = row0 + 4 * v;
+          const int64_t rc = row < n ? row : n - 1;
+          const double xo = a.x_in[rc], ro = a.r_in[rc];
+          double dx = 0.0, dr = 0.0;
+          for (int e = 0; e < 4; ++e) {
+            const double bv = fbeta[16 * e + m];
+            dx = __builtin_fma(tile[1][(4 * v + rq) * LD + 16 * e + m], bv, dx);
+            dr = __builtin_fma(tile[0][(4 * v + rq) * LD + 16 * e + m], bv, dr);
+          }
+          dx = row_sum16(dx);
+          dr = row_sum16(dr);
+          if (m == 0 && row < n) {
+            a.x_out[row] = xo + dx;
+            a.r_out[row] = ro - dr;
+          }
+        }
+      }
     }
   }
   if constexpr (NG > 0) {
-    // this row group's partial: G_g[16 i + 4 v + rq][16 cb + m]
-    double* mine = a.rc.partials + ((size_t)blockIdx.x * C::RGRP + rg) * (NG * T2);
+    // H_g[16 e + 4 v + rq][16 cb + m]; one partial per work-group
+    double* mine = a.rc.partials + (size_t)blockIdx.x * (NG * T2);
     for (int g = 0; g < NG; ++g)
-      for (int i = 0; i < EPL; ++i)
-        for (int v = 0; v < 4; ++v) mine[g * T2 + (16 * i + 4 * v + rq) * TPI + 16 * cb + m] = acc[g][i][v];
+      for (int e = 0; e < 4; ++e)
+        for (int v = 0; v < 4; ++v) mine[g * T2 + (16 * e + 4 * v + rq) * TPI + 16 * cb + m] = acc[g][e][v];
   }
 }
 
@@ -2349,9 +2335,9 @@ hipError_t launch_update_gram(int nu, int ng, bool ident0, bool write_out, int t
 #define ECG_UG(NU, NG, ID, WR, TL, P0X)                                                   \
   if (nu == NU && ng == NG && ident0 == ID && write_out == WR && tail == TL &&             \
       (a.P[0] == a.X[0]) == P0X) {                                                         \
-    if constexpr (uses_cs(TPI))                                                            \
-      hipLaunchKernelGGL((k_update_gram_cs<TPI, S, NU, NG, ID, WR, P0X>), dim3(grid),      \
-                         dim3(cs_threads(TPI)), 0, st, a);                                 \
+    if constexpr (uses_cs(TPI))   /* one Gram partial per work-group of 4 waves */         \
+      hipLaunchKernelGGL((k_update_gram_mf<S, NU, NG, ID, WR, P0X>), dim3(grid * kCSGroups), \
+                         dim3(kThreads), 0, st, a);                                        \
     else                                                                                   \
       hipLaunchKernelGGL((k_update_gram<TPI, S, NU, NG, ID, WR, TL, P0X>), dim3(grid),     \
                          dim3(kThreads), 0, st, a);                                        \

@@ -200,3 +200,20 @@ def test_stats_account_every_kernel(E):
     assert st["xr_update"]["launches"] == info.iters or info.status != E.OK
     assert all(v["ms"] >= 0 for v in st.values())
     assert st["spmm"]["ms"] > 0 and st["cgs_gram"]["ms"] > 0
+
+
+@pytest.mark.parametrize("m,t,s,parts", [(48, 32, 2, (4, 8, 1)), (64, 64, 2, (8, 8, 1))])
+def test_mixed_precision_wide_blocks(E, m, t, s, parts):
+    # binary32 blocks of 32 and 64 stored columns (the 64-column updates run
+    # on the matrix cores)
+    p = P.poisson2d(m, t=t, parts=parts, seed=m)
+    A = p.scipy()
+    sol, dom = _setup(E, p, t, s, parts, precision=E.MIXED)
+    x, info = sol.solve(p.b, tol=1e-8, maxit=2000)
+    x = x.cpu().numpy()
+    assert info.status == E.OK
+    assert np.linalg.norm(p.b - A @ x) / np.linalg.norm(p.b) <= 1e-8
+    ref = O.sstep_srecg(A, dom, t, s, p.b, tol=1e-8)
+    assert _rel(x, ref.x) <= 1e-5
+    m32 = O.sstep_srecg(A, dom, t, s, p.b, tol=1e-8, basis_dtype=np.float32, inner_tol=1e-4)
+    assert abs(info.iters - m32.iters) <= max(3, 0.1 * m32.iters)
