@@ -161,6 +161,12 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #ifndef ECG_SP_WIDE
 #define ECG_SP_WIDE 1          // wide-gather product kernel for 16-column binary64 blocks
 #endif
+#ifndef ECG_MF32
+#define ECG_MF32 1             // 32-column block updates on the matrix cores as well
+#endif
+#ifndef ECG_MF_PF
+#define ECG_MF_PF 1            // matrix-core update: load the next step during this one
+#endif
 #ifndef ECG_MF_WPE
 #define ECG_MF_WPE 2
 #endif
@@ -1706,63 +1712,100 @@ __device__ __forceinline__ double pick(const double (&v)[EPL], int cb) {
   return r;
 }
 
-// Block update and Grams at 64 columns on the matrix cores.  A work-group
-// of four waves takes 16 rows per step; wave w owns output columns
-// 16 w .. 16 w + 15.  The update out = sum_b X_b C_b is a 16 x 64 by 64 x 16
+// Block update and Grams at 32 and 64 columns on the matrix cores.  A
+// row group of W = TPI / 16 waves takes 16 rows per step; wave w of it owns
+// output columns 16 w .. 16 w + 15 (a work-group of four waves holds 4 / W
+// row groups).  The update out = sum_b X_b C_b is a 16 x TPI by TPI x 16
 // product per wave and operand: MFMA f64 16x16x4 with the rows as M, the
 // input columns as K (four per instruction) and the wave's output columns
 // as N.  The B operands (this wave's slice of each coefficient matrix) stay
 // in registers for the whole launch; the A operands (row l % 16, column
-// 4 kk + l / 16 of X_b) come from an LDS tile the four waves fill with
-// their column slices.  The result lands in the natural layout (lane: row
-// 4 v + l / 16, column l % 16), which is the B operand of the Gram products
-// H_g = P_g^t out (K = rows) and the layout of the coalesced store.
-template <typename S, int NU, int NG, bool IDENT0, bool WRITE, bool P0X>
+// 4 kk + l / 16 of X_b) come from an LDS tile the row group's waves fill
+// with their column slices.  The result lands in the natural layout (lane:
+// row 4 v + l / 16, column l % 16), which is the B operand of the Gram
+// products H_g = P_g^t out (K = rows) and the layout of the coalesced store.
+template <int TPI, typename S, int NU, int NG, bool IDENT0, bool WRITE, bool P0X>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ECG_MF_WPE, ECG_MF_WPE)))
 void k_update_gram_mf(UGArgs<S> a) {
-  constexpr int TPI = 64, T2 = TPI * TPI, LD = TPI + 1;   // LD: padded tile rows
+  constexpr int T2 = TPI * TPI, LD = TPI + 1;   // LD: padded tile rows
+  constexpr int W = TPI / 16, RG = 4 / W, KQ = TPI / 4;
   constexpr int NCOEF = NU - (IDENT0 ? 1 : 0);
   constexpr int NX = NU;
   constexpr int NP = NG - (P0X ? 1 : 0);
   constexpr int NLD = NX + NP;
-  __shared__ double tile[NLD][16 * LD];
+  static_assert(RG * NLD * 16 * LD >= (RG > 1 ? NG * T2 : 0), "Gram exchange fits the tiles");
+  __shared__ double tile[RG][NLD][16 * LD];
   __shared__ double fbeta[TPI];
-  const int tid = threadIdx.x, lane = tid & 63, cb = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cb = wave % W, rg = wave / W;
   const int m = lane & 15, rq = lane >> 4;
+  double(*const tl)[16 * LD] = tile[rg];
 
   // B operands: cf[b][kk] = C[4 kk + l / 16][16 cb + l % 16]
-  double cf[NCOEF > 0 ? NCOEF : 1][16];
+  double cf[NCOEF > 0 ? NCOEF : 1][KQ];
   for (int b = 0; b < NCOEF; ++b) {
     const double* cm = a.C[b + (IDENT0 ? 1 : 0)];
-    for (int kk = 0; kk < 16; ++kk) cf[b][kk] = cm[(4 * kk + rq) * TPI + 16 * cb + m];
+    for (int kk = 0; kk < KQ; ++kk) cf[b][kk] = cm[(4 * kk + rq) * TPI + 16 * cb + m];
   }
   const bool fold = !IDENT0 && NU >= 2 && a.fold_beta != nullptr && a.status->breakdown == 0;
   if (fold)
     for (int idx = tid; idx < TPI; idx += blockDim.x) fbeta[idx] = a.fold_beta[idx];
 
-  d4 acc[NG > 0 ? NG : 1][4];
+  d4 acc[NG > 0 ? NG : 1][W];
   for (int g = 0; g < (NG > 0 ? NG : 1); ++g)
-    for (int e = 0; e < 4; ++e) acc[g][e] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int e = 0; e < W; ++e) acc[g][e] = d4{0.0, 0.0, 0.0, 0.0};
 
   const S* src[NLD];
   for (int b = 0; b < NX; ++b) src[b] = a.X[b];
   for (int g = 0; g < NP; ++g) src[NX + g] = a.P[g + (P0X ? 1 : 0)];
 
   const int64_t n = a.n;
-  const Steps sp = my_steps((n + 15) / 16);
-  for (int64_t step = sp.first; step < sp.end; step += sp.stride) {
-    const int64_t row0 = step * 16 + rq;
-    // this wave's column slice of every operand, natural layout
-    double cur[NLD][4];
+  const Steps sp = my_steps((n + 16 * RG - 1) / (16 * RG));
+  constexpr bool FOLDK = !IDENT0 && NU >= 2;
+  // this wave's column slice of every operand (natural layout) and, for the
+  // fold, x_in and r_in of the rows; with PF the next step's are loaded
+  // while this step's products run
+  // (measured: faster at 32 columns for binary32 blocks and for the
+  // binary64 kernels with Grams, slower for the binary64 pure updates, no
+  // gain at 64 columns)
+  constexpr bool PF = ECG_MF_PF && TPI == 32 && (sizeof(S) == 4 || NG > 0);
+  struct Ld {
+    double c[NLD][4];
+    double xo[FOLDK ? 4 : 1], ro[FOLDK ? 4 : 1];
+  };
+  // x_in and r_in are null when the launch carries no fold: the loads then
+  // read the first operand instead (at least 8 n bytes), and go unused
+  const double* xsrc = fold ? a.x_in : reinterpret_cast<const double*>(src[0]);
+  const double* rsrc = fold ? a.r_in : reinterpret_cast<const double*>(src[0]);
+  auto load_step = [&](int64_t st, Ld& d) {
+    const int64_t r0 = st * (16 * RG) + 16 * rg + rq;
     for (int v = 0; v < 4; ++v) {
-      const int64_t row = row0 + 4 * v;
+      const int64_t row = r0 + 4 * v;
       const int64_t rc = row < n ? row : n - 1;
       const double okf = opaque(row < n ? 1.0 : 0.0);
-      for (int b = 0; b < NLD; ++b) cur[b][v] = ld(src[b] + rc * TPI + 16 * cb + m) * okf;
+      for (int b = 0; b < NLD; ++b) d.c[b][v] = ld(src[b] + rc * TPI + 16 * cb + m) * okf;
+      if constexpr (FOLDK) {
+        d.xo[v] = xsrc[rc];
+        d.ro[v] = rsrc[rc];
+      }
     }
+  };
+  Ld nx;
+  if (PF && sp.first < sp.end) load_step(sp.first, nx);
+  for (int64_t step = sp.first; step < sp.end; step += sp.stride) {
+    const int64_t row0 = step * (16 * RG) + 16 * rg + rq;
+    Ld ldc;
+    if constexpr (PF) {
+      ldc = nx;
+      // past the last step the rows are clamped and the values unused
+      load_step(step + sp.stride, nx);
+    } else {
+      load_step(step, ldc);
+    }
+    const double(&cur)[NLD][4] = ldc.c;
     __syncthreads();   // the previous step's tile readers are done (and fbeta is set)
     for (int b = 0; b < NLD; ++b)
-      for (int v = 0; v < 4; ++v) tile[b][(4 * v + rq) * LD + 16 * cb + m] = cur[b][v];
+      for (int v = 0; v < 4; ++v) tl[b][(4 * v + rq) * LD + 16 * cb + m] = cur[b][v];
     __syncthreads();
 
     d4 o;
@@ -1770,7 +1813,7 @@ void k_update_gram_mf(UGArgs<S> a) {
     static_for<NCOEF>([&](auto bc) {
       constexpr int b = decltype(bc)::value;
       constexpr int xb = b + (IDENT0 ? 1 : 0);
-      for (int kk = 0; kk < 16; ++kk) o = mfma16(tile[xb][m * LD + 4 * kk + rq], cf[b][kk], o);
+      for (int kk = 0; kk < KQ; ++kk) o = mfma16(tl[xb][m * LD + 4 * kk + rq], cf[b][kk], o);
     });
 
     if constexpr (WRITE) {
@@ -1783,43 +1826,63 @@ void k_update_gram_mf(UGArgs<S> a) {
       static_for<NG>([&](auto gc) {
         constexpr int g = decltype(gc)::value;
         constexpr int slot = (P0X && g == 0) ? 0 : NX + g - (P0X ? 1 : 0);
-        for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < W; ++e)
           for (int v = 0; v < 4; ++v) {
-            const double pv = tile[slot][(4 * v + rq) * LD + 16 * e + m];
+            const double pv = tl[slot][(4 * v + rq) * LD + 16 * e + m];
             acc[g][e] = mfma16(pv, o[v], acc[g][e]);
           }
       });
     }
     if constexpr (!IDENT0 && NU >= 2) {
-      // x/r contribution of the previous block (X[1] = U, X[0] = A U): wave 0
-      // reads the full rows from the tiles
+      // x/r contribution of the previous block (X[1] = U, X[0] = A U): the
+      // row group's first wave reads the full rows from the tiles
       if (fold && cb == 0) {
         for (int v = 0; v < 4; ++v) {
           const int64_t row = row0 + 4 * v;
-          const int64_t rc = row < n ? row : n - 1;
-          const double xo = a.x_in[rc], ro = a.r_in[rc];
           double dx = 0.0, dr = 0.0;
-          for (int e = 0; e < 4; ++e) {
+          for (int e = 0; e < W; ++e) {
             const double bv = fbeta[16 * e + m];
-            dx = __builtin_fma(tile[1][(4 * v + rq) * LD + 16 * e + m], bv, dx);
-            dr = __builtin_fma(tile[0][(4 * v + rq) * LD + 16 * e + m], bv, dr);
+            dx = __builtin_fma(tl[1][(4 * v + rq) * LD + 16 * e + m], bv, dx);
+            dr = __builtin_fma(tl[0][(4 * v + rq) * LD + 16 * e + m], bv, dr);
           }
           dx = row_sum16(dx);
           dr = row_sum16(dr);
           if (m == 0 && row < n) {
-            a.x_out[row] = xo + dx;
-            a.r_out[row] = ro - dr;
+            a.x_out[row] = ldc.xo[v] + dx;
+            a.r_out[row] = ldc.ro[v] - dr;
           }
         }
       }
     }
   }
   if constexpr (NG > 0) {
-    // H_g[16 e + 4 v + rq][16 cb + m]; one partial per work-group
+    // H_g[16 e + 4 v + rq][16 cb + m]; one partial per work-group.  With
+    // two row groups, the second one's sums pass through LDS and the first
+    // adds them to its own (a fixed order).
     double* mine = a.rc.partials + (size_t)blockIdx.x * (NG * T2);
-    for (int g = 0; g < NG; ++g)
-      for (int e = 0; e < 4; ++e)
-        for (int v = 0; v < 4; ++v) mine[g * T2 + (16 * e + 4 * v + rq) * TPI + 16 * cb + m] = acc[g][e][v];
+    if constexpr (RG == 1) {
+      for (int g = 0; g < NG; ++g)
+        for (int e = 0; e < W; ++e)
+          for (int v = 0; v < 4; ++v)
+            mine[g * T2 + (16 * e + 4 * v + rq) * TPI + 16 * cb + m] = acc[g][e][v];
+    } else {
+      static_assert(RG == 2, "two row groups");
+      double* xch = &tile[0][0][0];
+      __syncthreads();
+      if (rg == 1)
+        for (int g = 0; g < NG; ++g)
+          for (int e = 0; e < W; ++e)
+            for (int v = 0; v < 4; ++v)
+              xch[g * T2 + (16 * e + 4 * v + rq) * TPI + 16 * cb + m] = acc[g][e][v];
+      __syncthreads();
+      if (rg == 0)
+        for (int g = 0; g < NG; ++g)
+          for (int e = 0; e < W; ++e)
+            for (int v = 0; v < 4; ++v) {
+              const int idx = g * T2 + (16 * e + 4 * v + rq) * TPI + 16 * cb + m;
+              mine[idx] = acc[g][e][v] + xch[idx];
+            }
+    }
   }
 }
 
@@ -2336,7 +2399,10 @@ hipError_t launch_update_gram(int nu, int ng, bool ident0, bool write_out, int t
   if (nu == NU && ng == NG && ident0 == ID && write_out == WR && tail == TL &&             \
       (a.P[0] == a.X[0]) == P0X) {                                                         \
     if constexpr (uses_cs(TPI))   /* one Gram partial per work-group of 4 waves */         \
-      hipLaunchKernelGGL((k_update_gram_mf<S, NU, NG, ID, WR, P0X>), dim3(grid * kCSGroups), \
+      hipLaunchKernelGGL((k_update_gram_mf<TPI, S, NU, NG, ID, WR, P0X>),                  \
+                         dim3(grid * kCSGroups), dim3(kThreads), 0, st, a);                \
+    else if constexpr (TPI == 32 && ECG_MF32)                                              \
+      hipLaunchKernelGGL((k_update_gram_mf<TPI, S, NU, NG, ID, WR, P0X>), dim3(grid),      \
                          dim3(kThreads), 0, st, a);                                        \
     else                                                                                   \
       hipLaunchKernelGGL((k_update_gram<TPI, S, NU, NG, ID, WR, TL, P0X>), dim3(grid),     \
