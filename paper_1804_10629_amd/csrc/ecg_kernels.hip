@@ -164,6 +164,9 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #ifndef ECG_MF32
 #define ECG_MF32 1             // 32-column block updates on the matrix cores as well
 #endif
+#ifndef ECG_MF16F
+#define ECG_MF16F 1            // 16-column binary32 block updates on the matrix cores
+#endif
 #ifndef ECG_MF_PF
 #define ECG_MF_PF 1            // matrix-core update: load the next step during this one
 #endif
@@ -1712,7 +1715,9 @@ __device__ __forceinline__ double pick(const double (&v)[EPL], int cb) {
   return r;
 }
 
-// Block update and Grams at 32 and 64 columns on the matrix cores.  A
+// Block update and Grams on the matrix cores (32 and 64 columns, and 16
+// columns for binary32 blocks; binary64 16-column blocks keep the VALU
+// kernel above, which already streams at the copy rate).  A
 // row group of W = TPI / 16 waves takes 16 rows per step; wave w of it owns
 // output columns 16 w .. 16 w + 15 (a work-group of four waves holds 4 / W
 // row groups).  The update out = sum_b X_b C_b is a 16 x TPI by TPI x 16
@@ -1733,7 +1738,7 @@ void k_update_gram_mf(UGArgs<S> a) {
   constexpr int NX = NU;
   constexpr int NP = NG - (P0X ? 1 : 0);
   constexpr int NLD = NX + NP;
-  static_assert(RG * NLD * 16 * LD >= (RG > 1 ? NG * T2 : 0), "Gram exchange fits the tiles");
+  static_assert(RG * NLD * 16 * LD >= (RG - 1) * NG * T2, "Gram exchange fits the tiles");
   __shared__ double tile[RG][NLD][16 * LD];
   __shared__ double fbeta[TPI];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1767,8 +1772,8 @@ void k_update_gram_mf(UGArgs<S> a) {
   // while this step's products run
   // (measured: faster at 32 columns for binary32 blocks and for the
   // binary64 kernels with Grams, slower for the binary64 pure updates, no
-  // gain at 64 columns)
-  constexpr bool PF = ECG_MF_PF && TPI == 32 && (sizeof(S) == 4 || NG > 0);
+  // gain at 64 columns; at 16 columns only binary32 blocks take this kernel)
+  constexpr bool PF = ECG_MF_PF && ((TPI == 32 && (sizeof(S) == 4 || NG > 0)) || TPI == 16);
   struct Ld {
     double c[NLD][4];
     double xo[FOLDK ? 4 : 1], ro[FOLDK ? 4 : 1];
@@ -1866,21 +1871,25 @@ void k_update_gram_mf(UGArgs<S> a) {
           for (int v = 0; v < 4; ++v)
             mine[g * T2 + (16 * e + 4 * v + rq) * TPI + 16 * cb + m] = acc[g][e][v];
     } else {
-      static_assert(RG == 2, "two row groups");
+      // row groups 1 .. RG-1 park their sums in LDS; row group 0 adds them
+      // in row-group order
       double* xch = &tile[0][0][0];
       __syncthreads();
-      if (rg == 1)
+      if (rg > 0)
         for (int g = 0; g < NG; ++g)
           for (int e = 0; e < W; ++e)
             for (int v = 0; v < 4; ++v)
-              xch[g * T2 + (16 * e + 4 * v + rq) * TPI + 16 * cb + m] = acc[g][e][v];
+              xch[(rg - 1) * NG * T2 + g * T2 + (16 * e + 4 * v + rq) * TPI + 16 * cb + m] =
+                  acc[g][e][v];
       __syncthreads();
       if (rg == 0)
         for (int g = 0; g < NG; ++g)
           for (int e = 0; e < W; ++e)
             for (int v = 0; v < 4; ++v) {
               const int idx = g * T2 + (16 * e + 4 * v + rq) * TPI + 16 * cb + m;
-              mine[idx] = acc[g][e][v] + xch[idx];
+              double sum = acc[g][e][v];
+              for (int r = 1; r < RG; ++r) sum += xch[(r - 1) * NG * T2 + idx];
+              mine[idx] = sum;
             }
     }
   }
@@ -2401,7 +2410,8 @@ hipError_t launch_update_gram(int nu, int ng, bool ident0, bool write_out, int t
     if constexpr (uses_cs(TPI))   /* one Gram partial per work-group of 4 waves */         \
       hipLaunchKernelGGL((k_update_gram_mf<TPI, S, NU, NG, ID, WR, P0X>),                  \
                          dim3(grid * kCSGroups), dim3(kThreads), 0, st, a);                \
-    else if constexpr (TPI == 32 && ECG_MF32)                                              \
+    else if constexpr ((TPI == 32 && ECG_MF32) ||                                         \
+                       (TPI == 16 && ECG_MF16F && sizeof(S) == 4))                          \
       hipLaunchKernelGGL((k_update_gram_mf<TPI, S, NU, NG, ID, WR, P0X>), dim3(grid),      \
                          dim3(kThreads), 0, st, a);                                        \
     else                                                                                   \
