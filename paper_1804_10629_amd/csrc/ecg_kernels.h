@@ -14,15 +14,19 @@ constexpr int kMaxS = 16;         // largest s supported by the x/r update
 
 // Blocks of at least ECG_CS_MIN_TPI stored columns (64: at 32 the
 // row-per-lane-group kernels are faster) use the column-split product
-// kernel (work-groups of cs_threads(TPI) threads in kCSGroups row groups,
-// each row group writing its own Gram partial) and the matrix-core block
-// update (kCSGroups times as many work-groups of four waves, one partial
-// each), so both write gram_partials(TPI, grid) partials.
+// kernel (row groups of four waves, each writing its own Gram partial;
+// cs_threads(TPI) threads per work-group: one row group, which measured
+// faster than two) and the matrix-core block update (work-groups of four
+// waves, one partial each), both launched with kCSGroups row groups per
+// unit of the grid, so both write gram_partials(TPI, grid) partials.
 #ifndef ECG_CS_MIN_TPI
 #define ECG_CS_MIN_TPI 64
 #endif
 constexpr int kCSGroups = 2;
-constexpr int cs_threads(int tpi) { return tpi == 64 ? 512 : 256; }
+#ifndef ECG_CS_THREADS64
+#define ECG_CS_THREADS64 256
+#endif
+constexpr int cs_threads(int tpi) { return tpi == 64 ? ECG_CS_THREADS64 : 256; }
 constexpr bool uses_cs(int tpi) { return tpi >= ECG_CS_MIN_TPI; }
 // Gram partials written by a launch of `grid` work-groups.
 constexpr int gram_partials(int tpi, int grid) { return uses_cs(tpi) ? grid * kCSGroups : grid; }

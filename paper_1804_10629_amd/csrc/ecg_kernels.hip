@@ -1704,7 +1704,7 @@ struct CsCfg {
   static constexpr int WROWS = 4 * RPL;
   static constexpr int WGROWS = WROWS * RGRP;
   static constexpr int T2 = TPI * TPI;
-  static_assert(RGRP == kCSGroups, "row groups per work-group");
+  static_assert(RGRP >= 1 && kCSGroups % RGRP == 0, "row groups per work-group");
 };
 
 // v[cb] for a wave-uniform runtime cb, without indexing a register array
@@ -2443,14 +2443,15 @@ template <int TPI, typename S, typename SA>
 hipError_t launch_spmm(bool grams, bool has_prev, int tail, const SpArgs<S, SA>& a, int grid,
                        hipStream_t st) {
   if constexpr (uses_cs(TPI)) {
-    const dim3 blk(cs_threads(TPI));
+    // kCSGroups row groups (one Gram partial each) per unit of `grid`
+    const dim3 blk(cs_threads(TPI)), g(grid * (kCSGroups / CsCfg<TPI>::RGRP));
     if (grams && tail != TAIL_SPMM) return hipErrorInvalidValue;
     if (!grams)
-      hipLaunchKernelGGL((k_spmm_cs<TPI, S, SA, false, false>), dim3(grid), blk, 0, st, a);
+      hipLaunchKernelGGL((k_spmm_cs<TPI, S, SA, false, false>), g, blk, 0, st, a);
     else if (has_prev)
-      hipLaunchKernelGGL((k_spmm_cs<TPI, S, SA, true, true>), dim3(grid), blk, 0, st, a);
+      hipLaunchKernelGGL((k_spmm_cs<TPI, S, SA, true, true>), g, blk, 0, st, a);
     else
-      hipLaunchKernelGGL((k_spmm_cs<TPI, S, SA, true, false>), dim3(grid), blk, 0, st, a);
+      hipLaunchKernelGGL((k_spmm_cs<TPI, S, SA, true, false>), g, blk, 0, st, a);
     return hipGetLastError();
   }
   if constexpr (ECG_SP_WIDE != 0 && TPI == 16 && std::is_same<S, double>::value &&
