@@ -1774,9 +1774,11 @@ void k_update_gram_mf(UGArgs<S> a) {
   // binary64 kernels with Grams, slower for the binary64 pure updates, no
   // gain at 64 columns; at 16 columns only binary32 blocks take this kernel)
   constexpr bool PF = ECG_MF_PF && ((TPI == 32 && (sizeof(S) == 4 || NG > 0)) || TPI == 16);
+  // x and r: lane l takes row 4 (l % 4) + l / 16 of the 16 (lanes l % 16 >= 4
+  // repeat those rows), so one instruction covers the row group's rows
   struct Ld {
     double c[NLD][4];
-    double xo[FOLDK ? 4 : 1], ro[FOLDK ? 4 : 1];
+    double xo, ro;
   };
   // x_in and r_in are null when the launch carries no fold: the loads then
   // read the first operand instead (at least 8 n bytes), and go unused
@@ -1789,12 +1791,21 @@ void k_update_gram_mf(UGArgs<S> a) {
       const int64_t rc = row < n ? row : n - 1;
       const double okf = opaque(row < n ? 1.0 : 0.0);
       for (int b = 0; b < NLD; ++b) d.c[b][v] = ld(src[b] + rc * TPI + 16 * cb + m) * okf;
-      if constexpr (FOLDK) {
-        d.xo[v] = xsrc[rc];
-        d.ro[v] = rsrc[rc];
-      }
+    }
+    if constexpr (FOLDK) {
+      const int64_t row = r0 + 4 * (m & 3);
+      const int64_t rc = row < n ? row : n - 1;
+      d.xo = xsrc[rc];
+      d.ro = rsrc[rc];
     }
   };
+  // a one-wave row group (16 columns) orders its own LDS accesses; wider
+  // row groups synchronise the work-group
+  auto rg_sync = [&]() {
+    if constexpr (W == 1) wsync();
+    else __syncthreads();
+  };
+  if constexpr (W == 1) __syncthreads();   // fbeta
   Ld nx;
   if (PF && sp.first < sp.end) load_step(sp.first, nx);
   for (int64_t step = sp.first; step < sp.end; step += sp.stride) {
@@ -1808,10 +1819,10 @@ void k_update_gram_mf(UGArgs<S> a) {
       load_step(step, ldc);
     }
     const double(&cur)[NLD][4] = ldc.c;
-    __syncthreads();   // the previous step's tile readers are done (and fbeta is set)
+    rg_sync();   // the previous step's tile readers are done (and fbeta is set)
     for (int b = 0; b < NLD; ++b)
       for (int v = 0; v < 4; ++v) tl[b][(4 * v + rq) * LD + 16 * cb + m] = cur[b][v];
-    __syncthreads();
+    rg_sync();
 
     d4 o;
     for (int v = 0; v < 4; ++v) o[v] = IDENT0 ? cur[0][v] : 0.0;
@@ -1842,8 +1853,8 @@ void k_update_gram_mf(UGArgs<S> a) {
       // x/r contribution of the previous block (X[1] = U, X[0] = A U): the
       // row group's first wave reads the full rows from the tiles
       if (fold && cb == 0) {
+        double dxm = 0.0, drm = 0.0;   // sums of row 4 (m % 4) + rq
         for (int v = 0; v < 4; ++v) {
-          const int64_t row = row0 + 4 * v;
           double dx = 0.0, dr = 0.0;
           for (int e = 0; e < W; ++e) {
             const double bv = fbeta[16 * e + m];
@@ -1852,10 +1863,13 @@ void k_update_gram_mf(UGArgs<S> a) {
           }
           dx = row_sum16(dx);
           dr = row_sum16(dr);
-          if (m == 0 && row < n) {
-            a.x_out[row] = ldc.xo[v] + dx;
-            a.r_out[row] = ldc.ro[v] - dr;
-          }
+          dxm = (m & 3) == v ? dx : dxm;
+          drm = (m & 3) == v ? dr : drm;
+        }
+        const int64_t row = row0 + 4 * (m & 3);
+        if (m < 4 && row < n) {
+          a.x_out[row] = ldc.xo + dxm;
+          a.r_out[row] = ldc.ro - drm;
         }
       }
     }
