@@ -772,10 +772,15 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
   for (int g = 0; g < NP; ++g) src[NX + g] = a.P[g + (P0X ? 1 : 0)];
 
   const int64_t n = a.n;
-  // operands of one wave step: [operand][q][e], zero on rows >= n; with the
-  // fold also x and r of the rows
-  auto load_step = [&](int64_t step, double (&v)[NLD][RPL][EPL], double (&vx)[RPL],
-                       double (&vr)[RPL]) {
+  // x_in and r_in are null when the launch carries no fold: the loads then
+  // read the first operand instead (at least 8 n bytes), and go unused
+  constexpr bool FOLDK = !IDENT0 && NU >= 2;
+  const double* xsrc = fold ? a.x_in : reinterpret_cast<const double*>(src[0]);
+  const double* rsrc = fold ? a.r_in : reinterpret_cast<const double*>(src[0]);
+  // operands of one wave step: [operand][q][e], zero on rows >= n; for the
+  // fold, x and r of row 4 (m % RPL) + rq (one row per lane, lanes with
+  // m >= RPL repeating them), so one instruction covers the step's rows
+  auto load_step = [&](int64_t step, double (&v)[NLD][RPL][EPL], double& vx, double& vr) {
     const int64_t row0 = step * C::WGROWS + wave * C::WROWS + rq;
     for (int q = 0; q < RPL; ++q) {
       const int64_t row = row0 + 4 * q;
@@ -783,16 +788,18 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
       const double okf = opaque(row < n ? 1.0 : 0.0);
       for (int b = 0; b < NLD; ++b)
         for (int e = 0; e < EPL; ++e) v[b][q][e] = ld(src[b] + rc * TPI + m + 16 * e) * okf;
-      if (fold) {
-        vx[q] = a.x_in[rc];
-        vr[q] = a.r_in[rc];
-      }
+    }
+    if constexpr (FOLDK) {
+      const int64_t row = row0 + 4 * (m % RPL);
+      const int64_t rc = row < n ? row : n - 1;
+      vx = xsrc[rc];
+      vr = rsrc[rc];
     }
   };
 
   constexpr bool PF = ECG_UG_PREFETCH != 0;
   double cur[NLD][RPL][EPL], nxt[PF ? NLD : 1][RPL][EPL];
-  double fx[RPL], fr[RPL], nfx[RPL], nfr[RPL];
+  double fx = 0.0, fr = 0.0, nfx = 0.0, nfr = 0.0;
   const Steps sp = my_steps((n + C::WGROWS - 1) / C::WGROWS);
   int64_t step = sp.first;
   bool have = step < sp.end;
@@ -807,6 +814,7 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
     if constexpr (!IDENT0 && NU >= 2) {
       if (fold) {
         const int64_t row0f = step * C::WGROWS + wave * C::WROWS + rq;
+        double dxm = 0.0, drm = 0.0;   // sums of row 4 (m % RPL) + rq
         for (int q = 0; q < RPL; ++q) {
           double dx = 0.0, dr = 0.0;
           for (int e = 0; e < EPL; ++e) {
@@ -816,11 +824,13 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
           }
           dx = row_sum16(dx);
           dr = row_sum16(dr);
-          const int64_t row = row0f + 4 * q;
-          if (m == 0 && row < n) {
-            a.x_out[row] = fx[q] + dx;
-            a.r_out[row] = fr[q] - dr;
-          }
+          dxm = (m % RPL) == q ? dx : dxm;
+          drm = (m % RPL) == q ? dr : drm;
+        }
+        const int64_t row = row0f + 4 * (m % RPL);
+        if (m < RPL && row < n) {
+          a.x_out[row] = fx + dxm;
+          a.r_out[row] = fr - drm;
         }
       }
     }
@@ -879,10 +889,8 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
         for (int b = 0; b < NLD; ++b)
           for (int q = 0; q < RPL; ++q)
             for (int e = 0; e < EPL; ++e) cur[b][q][e] = nxt[b][q][e];
-        for (int q = 0; q < RPL; ++q) {
-          fx[q] = nfx[q];
-          fr[q] = nfr[q];
-        }
+        fx = nfx;
+        fr = nfr;
       }
     } else {
       if (have_next) load_step(nstep, cur, fx, fr);
