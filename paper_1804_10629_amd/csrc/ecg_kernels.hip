@@ -179,6 +179,12 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #ifndef ECG_XR_RQ
 #define ECG_XR_RQ 4            // row sets per step of that kernel
 #endif
+#ifndef ECG_SPW32
+#define ECG_SPW32 1            // wide-gather product kernel for 32-column binary64 blocks
+#endif
+#ifndef ECG_SPW32_RQ
+#define ECG_SPW32_RQ 2         // row quads per step of that kernel
+#endif
 #ifndef ECG_SPWF_RQ
 #define ECG_SPWF_RQ 1          // 16-row sets per step of the binary32 wide-gather kernel
 #endif
@@ -1285,6 +1291,177 @@ __global__ ECG_SPMM_ATTR void k_spmm_wide(SpArgs<double, double> a) {
           lds[2 * T2 + idx] = (first ? 0.0 : lds[2 * T2 + idx]) + accE[v];
         }
         if (rq == 0) lds[3 * T2 + m] = (w == 0 ? 0.0 : lds[3 * T2 + m]) + av;
+      }
+      __syncthreads();
+    }
+    write_partial(lds, L, a.rc);
+  }
+}
+
+// The wide-gather form for 32-column binary64 blocks: a row (256 bytes) is
+// gathered by the 16 lanes of a DPP row with one 16-byte load each
+// (columns 2 (l % 16), 2 (l % 16) + 1), half the load instructions of two
+// 8-byte loads per lane; the chunk's (column, value) pairs are broadcast
+// within the DPP row (lanes l % 16 and l % 16 + 8 hold entry l % 8).  The
+// Gram epilogue takes columns l % 16 and l % 16 + 16 per lane (the MFMA
+// layout): A Z is moved there with ds_bpermute within the row's lanes.
+template <bool GRAMS, bool HAS_PREV>
+__global__ ECG_SPMM_ATTR void k_spmm_w32(SpArgs<double, double> a) {
+  constexpr int TPI = 32, EPL = 2, T2 = TPI * TPI, L = 3 * T2 + TPI;
+  constexpr int RQ = ECG_SPW32_RQ;               // row quads per wave step
+  constexpr int WROWS = 4 * RQ, NWAVE = kThreads / 64, WGROWS = WROWS * NWAVE;
+  constexpr int LDSN = GRAMS ? L : 1;
+  __shared__ double lds[LDSN];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = lane & 15, rq = lane >> 4;
+
+  d4 accG[EPL][EPL], accF[EPL][EPL], accE[EPL][EPL];
+  double av[EPL];
+  for (int i = 0; i < EPL; ++i) {
+    av[i] = 0.0;
+    for (int j = 0; j < EPL; ++j) {
+      accG[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accF[i][j] = accG[i][j];
+      accE[i][j] = accG[i][j];
+    }
+  }
+  const int64_t n = a.n;
+  const int nnz_last = a.rowptr[n] - 1;
+  const Steps sp = my_steps((n + WGROWS - 1) / WGROWS);
+
+  struct RowPtr {
+    int p0[RQ], p1[RQ];
+  };
+  struct Head {              // raw chunk: entry l % 8 of each row quad's row
+    int col[RQ];
+    double val[RQ];
+  };
+  auto row_of = [&](int64_t step, int q) { return step * WGROWS + wave * WROWS + rq + 4 * q; };
+  auto load_rowptr = [&](int64_t step, RowPtr& rp) {
+    for (int q = 0; q < RQ; ++q) {
+      const int64_t row = row_of(step, q);
+      const int64_t rc = row < n ? row : n - 1;
+      rp.p0[q] = ld_s(a.rowptr + rc);
+      rp.p1[q] = ld_s(a.rowptr + rc + 1);
+    }
+  };
+  auto load_chunk = [&](const RowPtr& rp, int c, Head& h) {
+    for (int q = 0; q < RQ; ++q) {
+      const int idc = min(rp.p0[q] + c + (m & 7), nnz_last);
+      h.col[q] = ld_s(a.colind + idc);
+      h.val[q] = ld_s(a.vals + idc);
+    }
+  };
+  auto gather = [&](const RowPtr& rp, int c, const Head& h, double (&y)[RQ][2]) {
+    int offw[RQ];
+    double valb[RQ];
+    for (int q = 0; q < RQ; ++q) {
+      const bool ok = rp.p0[q] + c + (m & 7) < rp.p1[q];
+      offw[q] = ok ? h.col[q] : 0;
+      valb[q] = h.val[q] * opaque(ok ? 1.0 : 0.0);
+    }
+    static_for<8>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      for (int q = 0; q < RQ; ++q) {
+        const int col = bcast32<j>(offw[q]);
+        const double vj = bcast64<j>(valb[q]);
+        const double2 z = *reinterpret_cast<const double2*>(a.Z + (int64_t)col * TPI + 2 * m);
+        y[q][0] = __builtin_fma(vj, z.x, y[q][0]);
+        y[q][1] = __builtin_fma(vj, z.y, y[q][1]);
+      }
+    });
+  };
+
+  RowPtr rp_cur, rp_nxt;
+  Head h_cur;
+  int64_t step = sp.first;
+  if (step < sp.end) {
+    load_rowptr(step, rp_cur);
+    load_chunk(rp_cur, 0, h_cur);
+    load_rowptr(step + sp.stride, rp_nxt);   // rows past the end are clamped
+  }
+  for (; step < sp.end; step += sp.stride) {
+    Head h_nxt;
+    RowPtr rp_nn;
+    load_chunk(rp_nxt, 0, h_nxt);
+    load_rowptr(step + 2 * sp.stride, rp_nn);
+    double z[RQ][EPL], pz[RQ][EPL], rv[RQ], okm[RQ];
+    if constexpr (GRAMS) {
+      for (int q = 0; q < RQ; ++q) {
+        const int64_t row = row_of(step, q);
+        const int64_t rc = row < n ? row : n - 1;
+        okm[q] = opaque(row < n ? 1.0 : 0.0);
+        rv[q] = ld_s(a.rvec + rc);
+        for (int e = 0; e < EPL; ++e) {
+          z[q][e] = a.Z[rc * TPI + m + 16 * e];
+          pz[q][e] = HAS_PREV ? ld_s(a.AZprev + rc * TPI + m + 16 * e) : 0.0;
+        }
+      }
+    }
+    double y[RQ][2];
+    for (int q = 0; q < RQ; ++q) y[q][0] = y[q][1] = 0.0;
+    gather(rp_cur, 0, h_cur, y);
+    int len = 0;
+    for (int q = 0; q < RQ; ++q) len = max(len, rp_cur.p1[q] - rp_cur.p0[q]);
+    for (int c = 8; c < len; c += 8) {   // rows longer than one chunk
+      Head h;
+      load_chunk(rp_cur, c, h);
+      gather(rp_cur, c, h, y);
+    }
+    for (int q = 0; q < RQ; ++q) {
+      const int64_t row = row_of(step, q);
+      if (row < n) {
+        double2 v;
+        v.x = y[q][0];
+        v.y = y[q][1];
+        *reinterpret_cast<double2*>(a.AZ + row * TPI + 2 * m) = v;
+      }
+    }
+    if constexpr (GRAMS) {
+      for (int q = 0; q < RQ; ++q) {
+        // A Z at column m + 16 e of this lane's row: lane (m >> 1) + 8 e of
+        // the same DPP row, element m & 1
+        double yk[EPL];
+        for (int e = 0; e < EPL; ++e) {
+          const int src = 16 * rq + (m >> 1) + 8 * e;
+          const double e0 = bperm64(src, y[q][0]), e1 = bperm64(src, y[q][1]);
+          yk[e] = ((m & 1) ? e1 : e0) * okm[q];
+        }
+        for (int i = 0; i < EPL; ++i) {
+          av[i] = __builtin_fma(z[q][i] * okm[q], rv[q], av[i]);
+          for (int j = 0; j < EPL; ++j) {
+            accG[i][j] = mfma16(z[q][i], yk[j], accG[i][j]);
+            accF[i][j] = mfma16(yk[i], yk[j], accF[i][j]);
+            if constexpr (HAS_PREV) accE[i][j] = mfma16(pz[q][i], yk[j], accE[i][j]);
+          }
+        }
+      }
+    }
+    h_cur = h_nxt;
+    rp_cur = rp_nxt;
+    rp_nxt = rp_nn;
+  }
+  if constexpr (GRAMS) {
+    for (int i = 0; i < EPL; ++i) {
+      av[i] += __shfl_xor(av[i], 16, 64);
+      av[i] += __shfl_xor(av[i], 32, 64);
+    }
+    for (int w = 0; w < NWAVE; ++w) {
+      if (wave == w) {
+        for (int i = 0; i < EPL; ++i)
+          for (int j = 0; j < EPL; ++j)
+            for (int v = 0; v < 4; ++v) {
+              const int idx = (16 * i + 4 * v + rq) * TPI + 16 * j + m;
+              const bool first = (w == 0);
+              lds[idx] = (first ? 0.0 : lds[idx]) + accG[i][j][v];
+              lds[T2 + idx] = (first ? 0.0 : lds[T2 + idx]) + accF[i][j][v];
+              lds[2 * T2 + idx] = (first ? 0.0 : lds[2 * T2 + idx]) + accE[i][j][v];
+            }
+        if (rq == 0)
+          for (int i = 0; i < EPL; ++i) {
+            const int idx = 3 * T2 + 16 * i + m;
+            lds[idx] = (w == 0 ? 0.0 : lds[idx]) + av[i];
+          }
       }
       __syncthreads();
     }
@@ -2497,6 +2674,20 @@ hipError_t launch_spmm(bool grams, bool has_prev, int tail, const SpArgs<S, SA>&
     else
       hipLaunchKernelGGL((k_spmm_widef<true, false>), dim3(grid), dim3(kThreads), 0, st, a);
     return hipGetLastError();
+  }
+  if constexpr (ECG_SPW32 != 0 && TPI == 32 && std::is_same<S, double>::value &&
+                std::is_same<SA, double>::value) {
+    if (!grams) {
+      hipLaunchKernelGGL((k_spmm_w32<false, false>), dim3(grid), dim3(kThreads), 0, st, a);
+      return hipGetLastError();
+    }
+    if (tail == TAIL_SPMM) {
+      if (has_prev)
+        hipLaunchKernelGGL((k_spmm_w32<true, true>), dim3(grid), dim3(kThreads), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_spmm_w32<true, false>), dim3(grid), dim3(kThreads), 0, st, a);
+      return hipGetLastError();
+    }
   }
   if constexpr (TPI == 16 && (ECG_SP_DEEP == 2 || (ECG_SP_DEEP == 1 && sizeof(S) == 4))) {
     if (grams && tail != TAIL_SPMM) return hipErrorInvalidValue;
