@@ -180,7 +180,7 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #define ECG_XR_RQ 4            // row sets per step of that kernel
 #endif
 #ifndef ECG_SPW32
-#define ECG_SPW32 1            // wide-gather product kernel for 32-column binary64 blocks
+#define ECG_SPW32 1            // wide-gather product kernels for 32-column blocks
 #endif
 #ifndef ECG_SPW32_RQ
 #define ECG_SPW32_RQ 2         // row quads per step of that kernel
@@ -1469,6 +1469,190 @@ __global__ ECG_SPMM_ATTR void k_spmm_w32(SpArgs<double, double> a) {
   }
 }
 
+// The wide-gather form for 32-column binary32 blocks: a row (128 bytes) is
+// gathered by 8 lanes with one 16-byte load each (columns 4 (l % 8) ..
+// 4 (l % 8) + 3), 8 rows per wave instruction, RQ such row sets per step;
+// lane l holds entry l % 8 of its row's chunk, broadcast within the half
+// DPP row.  Products are accumulated in binary64 and rounded once.  For the
+// Grams the wave's rounded A Z tile goes through LDS (its own region,
+// ordered within the wave) into the MFMA layout.
+template <bool GRAMS, bool HAS_PREV>
+__global__ ECG_SPMM_ATTR void k_spmm_w32f(SpArgs<float, float> a) {
+  constexpr int TPI = 32, EPL = 2, T2 = TPI * TPI, L = 3 * T2 + TPI;
+  constexpr int RQ = 2;                          // 8-row sets per wave step
+  constexpr int WROWS = 8 * RQ, NWAVE = kThreads / 64, WGROWS = WROWS * NWAVE;
+  constexpr int LDSN = GRAMS ? L : 1;
+  constexpr int TLD = TPI + 1;                   // padded rows of the A Z tile (floats)
+  __shared__ double lds[LDSN];
+  __shared__ float azt[GRAMS ? NWAVE * WROWS * TLD : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ri = lane >> 3, pp = lane & 7;       // gather layout
+  const int m = lane & 15, rq = lane >> 4;       // MFMA layout
+  const bool upper = (lane & 8) != 0;
+  float* tile = azt + (GRAMS ? wave * WROWS * TLD : 0);
+
+  d4 accG[EPL][EPL], accF[EPL][EPL], accE[EPL][EPL];
+  double av[EPL];
+  for (int i = 0; i < EPL; ++i) {
+    av[i] = 0.0;
+    for (int j = 0; j < EPL; ++j) {
+      accG[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accF[i][j] = accG[i][j];
+      accE[i][j] = accG[i][j];
+    }
+  }
+  const int64_t n = a.n;
+  const int nnz_last = a.rowptr[n] - 1;
+  const Steps sp = my_steps((n + WGROWS - 1) / WGROWS);
+
+  struct RowPtr {
+    int p0[RQ], p1[RQ];
+  };
+  struct Head {
+    int col[RQ];
+    float val[RQ];
+  };
+  auto row_of = [&](int64_t step, int q) { return step * WGROWS + wave * WROWS + ri + 8 * q; };
+  auto load_rowptr = [&](int64_t step, RowPtr& rp) {
+    for (int q = 0; q < RQ; ++q) {
+      const int64_t row = row_of(step, q);
+      const int64_t rc = row < n ? row : n - 1;
+      rp.p0[q] = ld_s(a.rowptr + rc);
+      rp.p1[q] = ld_s(a.rowptr + rc + 1);
+    }
+  };
+  auto load_chunk = [&](const RowPtr& rp, int c, Head& h) {
+    for (int q = 0; q < RQ; ++q) {
+      const int idc = min(rp.p0[q] + c + pp, nnz_last);
+      h.col[q] = ld_s(a.colind + idc);
+      h.val[q] = ld_s(a.vals + idc);
+    }
+  };
+  auto gather = [&](const RowPtr& rp, int c, const Head& h, double (&y)[RQ][4]) {
+    int offw[RQ], valw[RQ];
+    for (int q = 0; q < RQ; ++q) {
+      const bool ok = rp.p0[q] + c + pp < rp.p1[q];
+      offw[q] = ok ? h.col[q] : 0;
+      valw[q] = __builtin_bit_cast(int, h.val[q] * opaque(ok ? 1.0f : 0.0f));
+    }
+    static_for<8>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      for (int q = 0; q < RQ; ++q) {
+        const int col = bcast8_32<j>(offw[q], upper);
+        const double vj = static_cast<double>(__builtin_bit_cast(float, bcast8_32<j>(valw[q], upper)));
+        const float4 z = *reinterpret_cast<const float4*>(a.Z + (int64_t)col * TPI + 4 * pp);
+        y[q][0] = __builtin_fma(vj, static_cast<double>(z.x), y[q][0]);
+        y[q][1] = __builtin_fma(vj, static_cast<double>(z.y), y[q][1]);
+        y[q][2] = __builtin_fma(vj, static_cast<double>(z.z), y[q][2]);
+        y[q][3] = __builtin_fma(vj, static_cast<double>(z.w), y[q][3]);
+      }
+    });
+  };
+
+  RowPtr rp_cur, rp_nxt;
+  Head h_cur;
+  int64_t step = sp.first;
+  if (step < sp.end) {
+    load_rowptr(step, rp_cur);
+    load_chunk(rp_cur, 0, h_cur);
+    load_rowptr(step + sp.stride, rp_nxt);   // rows past the end are clamped
+  }
+  for (; step < sp.end; step += sp.stride) {
+    Head h_nxt;
+    RowPtr rp_nn;
+    load_chunk(rp_nxt, 0, h_nxt);
+    load_rowptr(step + 2 * sp.stride, rp_nn);
+    // Gram operands in the MFMA layout: row 4 k + rq of the step, column m + 16 e
+    double z[4][EPL], pz[4][EPL], rv[4], okm[4];
+    if constexpr (GRAMS) {
+      for (int k = 0; k < 4; ++k) {
+        const int64_t row = step * WGROWS + wave * WROWS + rq + 4 * k;
+        const int64_t rc = row < n ? row : n - 1;
+        okm[k] = opaque(row < n ? 1.0 : 0.0);
+        rv[k] = ld_s(a.rvec + rc);
+        for (int e = 0; e < EPL; ++e) {
+          z[k][e] = static_cast<double>(a.Z[rc * TPI + m + 16 * e]);
+          pz[k][e] = HAS_PREV ? static_cast<double>(ld_s(a.AZprev + rc * TPI + m + 16 * e)) : 0.0;
+        }
+      }
+    }
+    double y[RQ][4];
+    for (int q = 0; q < RQ; ++q) y[q][0] = y[q][1] = y[q][2] = y[q][3] = 0.0;
+    gather(rp_cur, 0, h_cur, y);
+    int len = 0;
+    for (int q = 0; q < RQ; ++q) len = max(len, rp_cur.p1[q] - rp_cur.p0[q]);
+    for (int c = 8; c < len; c += 8) {   // rows longer than one chunk
+      Head h;
+      load_chunk(rp_cur, c, h);
+      gather(rp_cur, c, h, y);
+    }
+    float4 yf[RQ];
+    for (int q = 0; q < RQ; ++q) {
+      yf[q].x = static_cast<float>(y[q][0]);
+      yf[q].y = static_cast<float>(y[q][1]);
+      yf[q].z = static_cast<float>(y[q][2]);
+      yf[q].w = static_cast<float>(y[q][3]);
+      const int64_t row = row_of(step, q);
+      if (row < n) *reinterpret_cast<float4*>(a.AZ + row * TPI + 4 * pp) = yf[q];
+    }
+    if constexpr (GRAMS) {
+      // the stored (rounded) A Z: tile row 8 q + ri, then read back in the
+      // MFMA layout (row 4 k + rq, columns m and m + 16)
+      wsync();   // the previous step's tile reads are done
+      for (int q = 0; q < RQ; ++q) {
+        float* t = tile + (8 * q + ri) * TLD + 4 * pp;
+        t[0] = yf[q].x;
+        t[1] = yf[q].y;
+        t[2] = yf[q].z;
+        t[3] = yf[q].w;
+      }
+      wsync();
+      for (int k = 0; k < 4; ++k) {
+        double yk[EPL];
+        for (int e = 0; e < EPL; ++e)
+          yk[e] = static_cast<double>(tile[(4 * k + rq) * TLD + m + 16 * e]) * okm[k];
+        for (int i = 0; i < EPL; ++i) {
+          av[i] = __builtin_fma(z[k][i] * okm[k], rv[k], av[i]);
+          for (int j = 0; j < EPL; ++j) {
+            accG[i][j] = mfma16(z[k][i], yk[j], accG[i][j]);
+            accF[i][j] = mfma16(yk[i], yk[j], accF[i][j]);
+            if constexpr (HAS_PREV) accE[i][j] = mfma16(pz[k][i], yk[j], accE[i][j]);
+          }
+        }
+      }
+    }
+    h_cur = h_nxt;
+    rp_cur = rp_nxt;
+    rp_nxt = rp_nn;
+  }
+  if constexpr (GRAMS) {
+    for (int i = 0; i < EPL; ++i) {
+      av[i] += __shfl_xor(av[i], 16, 64);
+      av[i] += __shfl_xor(av[i], 32, 64);
+    }
+    for (int w = 0; w < NWAVE; ++w) {
+      if (wave == w) {
+        for (int i = 0; i < EPL; ++i)
+          for (int j = 0; j < EPL; ++j)
+            for (int v = 0; v < 4; ++v) {
+              const int idx = (16 * i + 4 * v + rq) * TPI + 16 * j + m;
+              const bool first = (w == 0);
+              lds[idx] = (first ? 0.0 : lds[idx]) + accG[i][j][v];
+              lds[T2 + idx] = (first ? 0.0 : lds[T2 + idx]) + accF[i][j][v];
+              lds[2 * T2 + idx] = (first ? 0.0 : lds[2 * T2 + idx]) + accE[i][j][v];
+            }
+        if (rq == 0)
+          for (int i = 0; i < EPL; ++i) {
+            const int idx = 3 * T2 + 16 * i + m;
+            lds[idx] = (w == 0 ? 0.0 : lds[idx]) + av[i];
+          }
+      }
+      __syncthreads();
+    }
+    write_partial(lds, L, a.rc);
+  }
+}
+
 // The wide-gather form for 16-column binary32 blocks: a row is 64 bytes, so
 // 4 lanes per row gather 16 bytes each (columns 4 (l % 4) .. 4 (l % 4) + 3)
 // and each lane holds two entries (l % 4 and l % 4 + 4) of its row's chunk,
@@ -2686,6 +2870,20 @@ hipError_t launch_spmm(bool grams, bool has_prev, int tail, const SpArgs<S, SA>&
         hipLaunchKernelGGL((k_spmm_w32<true, true>), dim3(grid), dim3(kThreads), 0, st, a);
       else
         hipLaunchKernelGGL((k_spmm_w32<true, false>), dim3(grid), dim3(kThreads), 0, st, a);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (ECG_SPW32 != 0 && TPI == 32 && std::is_same<S, float>::value &&
+                std::is_same<SA, float>::value) {
+    if (!grams) {
+      hipLaunchKernelGGL((k_spmm_w32f<false, false>), dim3(grid), dim3(kThreads), 0, st, a);
+      return hipGetLastError();
+    }
+    if (tail == TAIL_SPMM) {
+      if (has_prev)
+        hipLaunchKernelGGL((k_spmm_w32f<true, true>), dim3(grid), dim3(kThreads), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_spmm_w32f<true, false>), dim3(grid), dim3(kThreads), 0, st, a);
       return hipGetLastError();
     }
   }

@@ -3,8 +3,8 @@ benchmark uses (default grid, stream and options).
 
 * 128^3 skyscraper (t = 16, s = 4) and 128^3 anisotropic (t = 32, s = 4):
   the first s-step iteration is compared element by element with the
-  oracle's (x_1 over all 2.1M rows, and the basis it built), in the FP64 and
-  the mixed form.
+  oracle's (x_1 over all 2.1M rows; at 16 columns also the basis it built),
+  in the FP64 and the mixed form.
 * 128^3 skyscraper: a full solve, its true residual recomputed on the CPU.
 * 256^3 random blocks (t = 64, s = 2, 16.8M rows): too large for the oracle;
   the first iteration is checked against properties that hold at any size
@@ -80,15 +80,19 @@ def test_skyscraper_full_solve(E, sky):
     sol.close()
 
 
-def test_anisotropic_first_iteration(E):
+@pytest.mark.parametrize("mixed", [False, True])
+def test_anisotropic_first_iteration(E, mixed):
     p = P.CONFIGS["C3"]()
     A = p.scipy()
     dom = O.partition_grid(p.shape, p.parts)
-    ref = O.sstep_srecg(A, dom, p.t, p.s, p.b, tol=p.tol, maxit=1, record=True)
-    sol, _ = _device_solver(E, p)
+    kw = {"basis_dtype": np.float32, "inner_tol": 1e-4} if mixed else {}
+    ref = O.sstep_srecg(A, dom, p.t, p.s, p.b, tol=p.tol, maxit=1, record=True, **kw)
+    sol, _ = _device_solver(E, p, precision=E.MIXED if mixed else E.FP64)
     x, info = sol.solve(p.b, tol=p.tol, maxit=1)
     xr = ref.extra["xs"][1]
-    assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e-10 * np.linalg.norm(xr)
+    rel = np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr)
+    print(f"x_1 relative difference {rel:.2e}")
+    assert rel <= (1e-6 if mixed else 1e-10)
     sol.close()
 
 
