@@ -248,3 +248,28 @@ def test_msdo_mixed_precision(E, poisson):
     assert info.status == E.OK and info.restarts >= 1
     assert np.linalg.norm(p.b - A @ x) / np.linalg.norm(p.b) <= 1e-8
     sol.close()
+
+
+@pytest.mark.parametrize("m,t,s,parts,variant,orth", [
+    (48, 32, 2, (4, 8, 1), "srecg2", "acholqr"), (64, 64, 2, (8, 8, 1), "srecg2", "acholqr"),
+    (64, 64, 1, (8, 8, 1), "msdo", "acholqr"), (64, 64, 2, (8, 8, 1), "srecg", "precholqr")])
+def test_variants_mixed_wide_blocks(E, m, t, s, parts, variant, orth):
+    # binary32 blocks of 32 and 64 columns through the Gram/update chunks,
+    # the MSDO restart passes and the Pre-CholQR scaling (all on the matrix
+    # cores at these widths)
+    p = P.poisson2d(m, t=t, parts=parts, seed=m + 3)
+    A = p.scipy()
+    dom = O.partition_grid(p.shape, parts)
+    var = {"srecg": E.SRECG, "srecg2": E.SRECG2, "msdo": E.MSDO}[variant]
+    sol = E.Solver(p.rowptr, p.colind, p.vals, dom, t, s, variant=var, precision=E.MIXED,
+                   orth=E.PRECHOLQR if orth == "precholqr" else E.ACHOLQR)
+    x, info = sol.solve(p.b, tol=1e-8, maxit=2000)
+    x = x.cpu().numpy()
+    assert info.status == E.OK
+    assert np.linalg.norm(p.b - A @ x) / np.linalg.norm(p.b) <= 1e-8
+    ref = O.sstep_srecg(A, dom, t, s, p.b, tol=1e-8, variant=variant, orth=orth)
+    assert _rel(x, ref.x) <= 1e-5
+    m32 = O.sstep_srecg(A, dom, t, s, p.b, tol=1e-8, variant=variant, orth=orth,
+                        basis_dtype=np.float32, inner_tol=1e-4)
+    assert abs(info.iters - m32.iters) <= max(3, m32.iters // 10), (info.iters, m32.iters)
+    sol.close()
