@@ -185,6 +185,9 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #ifndef ECG_SPW32_RQ
 #define ECG_SPW32_RQ 2         // row quads per step of that kernel
 #endif
+#ifndef ECG_CS_ZLDS
+#define ECG_CS_ZLDS 1          // column-split product: Z and A Z_prev column blocks via LDS
+#endif
 #ifndef ECG_SPWF_RQ
 #define ECG_SPWF_RQ 1          // 16-row sets per step of the binary32 wide-gather kernel
 #endif
@@ -2284,8 +2287,15 @@ void k_spmm_cs(SpArgs<S, SA> a) {
   using C = CsCfg<TPI>;
   constexpr int EPL = C::EPL, RPL = C::RPL, T2 = C::T2;
   constexpr int L = 3 * T2 + TPI;
-  // A Z rows of the current step, shared by the waves of a row group (F Gram)
-  __shared__ double yt[GRAMS ? 2 : 1][GRAMS ? C::RGRP * C::WROWS * TPI : 1];
+  // A Z rows of the current step, shared by the waves of a row group (F Gram);
+  // for binary64 blocks also Z and A Z_prev: each wave loads its own column
+  // block and reads the others from LDS (measured: 20.6 -> 17.1 ms at 256^3;
+  // no gain for binary32 blocks, whose rows are half as long)
+  constexpr int TS = GRAMS ? C::RGRP * C::WROWS * TPI : 1;
+  constexpr bool ZL = ECG_CS_ZLDS != 0 && GRAMS && sizeof(S) == 8;
+  __shared__ double yt[GRAMS ? 2 : 1][TS];
+  __shared__ double zt[ZL ? 2 : 1][ZL ? TS : 1];
+  __shared__ double pzt[ZL && HAS_PREV ? 2 : 1][ZL && HAS_PREV ? TS : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m = lane & 15, rq = lane >> 4;
   const int cb = wave % EPL, rg = wave / EPL;
@@ -2372,9 +2382,11 @@ void k_spmm_cs(SpArgs<S, SA> a) {
       for (int q = 0; q < RPL; ++q) {
         rv[q] = ld_s(a.rvec + rowc[q]) * okf[q];
         for (int e = 0; e < EPL; ++e) {
-          z[q][e] = ld(a.Z + rowc[q] * TPI + m + 16 * e) * okf[q];
+          if (ZL && e > 0) break;   // own column block only (index 0 holds it)
+          const int col = ZL ? 16 * cb + m : m + 16 * e;
+          z[q][e] = ld(a.Z + rowc[q] * TPI + col) * okf[q];
           if constexpr (HAS_PREV)
-            pz[q][e] = static_cast<double>(ld_s(a.AZprev + rowc[q] * TPI + m + 16 * e)) * okf[q];
+            pz[q][e] = static_cast<double>(ld_s(a.AZprev + rowc[q] * TPI + col)) * okf[q];
           else
             pz[q][e] = 0.0;
         }
@@ -2399,7 +2411,24 @@ void k_spmm_cs(SpArgs<S, SA> a) {
         y[q] = static_cast<double>(static_cast<S>(y[q])) * okf[q];
         t[(rq + 4 * q) * TPI + 16 * cb + m] = y[q];
       }
+      if constexpr (ZL) {
+        double* tz = &zt[buf][rg * C::WROWS * TPI];
+        double* tp = &pzt[HAS_PREV ? buf : 0][HAS_PREV ? rg * C::WROWS * TPI : 0];
+        for (int q = 0; q < RPL; ++q) {
+          tz[(rq + 4 * q) * TPI + 16 * cb + m] = z[q][0];
+          if constexpr (HAS_PREV) tp[(rq + 4 * q) * TPI + 16 * cb + m] = pz[q][0];
+        }
+      }
       __syncthreads();
+      if constexpr (ZL) {
+        const double* tz = &zt[buf][rg * C::WROWS * TPI];
+        const double* tp = &pzt[HAS_PREV ? buf : 0][HAS_PREV ? rg * C::WROWS * TPI : 0];
+        for (int q = 0; q < RPL; ++q)
+          for (int e = 0; e < EPL; ++e) {
+            z[q][e] = tz[(rq + 4 * q) * TPI + 16 * e + m];
+            if constexpr (HAS_PREV) pz[q][e] = tp[(rq + 4 * q) * TPI + 16 * e + m];
+          }
+      }
       for (int q = 0; q < RPL; ++q) {
         av = __builtin_fma(pick<EPL>(z[q], cb), rv[q], av);
         for (int i = 0; i < EPL; ++i) {
