@@ -167,6 +167,9 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #ifndef ECG_MF16F
 #define ECG_MF16F 1            // 16-column binary32 block updates on the matrix cores
 #endif
+#ifndef ECG_MF16D
+#define ECG_MF16D 1            // 16-column binary64 launches with Grams on the matrix cores
+#endif
 #ifndef ECG_MF_PF
 #define ECG_MF_PF 1            // matrix-core update: load the next step during this one
 #endif
@@ -782,10 +785,13 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
 
   const int64_t n = a.n;
   // x_in and r_in are null when the launch carries no fold: the loads then
-  // read the first operand instead (at least 8 n bytes), and go unused
+  // read the first operand instead, and go unused
   constexpr bool FOLDK = !IDENT0 && NU >= 2;
   const double* xsrc = fold ? a.x_in : reinterpret_cast<const double*>(src[0]);
   const double* rsrc = fold ? a.r_in : reinterpret_cast<const double*>(src[0]);
+  // without a fold, row rc reads the first 8 bytes of its own row of X[0]
+  // (loaded anyway): no extra traffic
+  const int64_t xstride = fold ? 1 : (int64_t)(TPI * sizeof(S) / 8);
   // operands of one wave step: [operand][q][e], zero on rows >= n; for the
   // fold, x and r of row 4 (m % RPL) + rq (one row per lane, lanes with
   // m >= RPL repeating them), so one instruction covers the step's rows
@@ -801,8 +807,8 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
     if constexpr (FOLDK) {
       const int64_t row = row0 + 4 * (m % RPL);
       const int64_t rc = row < n ? row : n - 1;
-      vx = xsrc[rc];
-      vr = rsrc[rc];
+      vx = xsrc[rc * xstride];
+      vr = rsrc[rc * xstride];
     }
   };
 
@@ -2087,9 +2093,9 @@ __device__ __forceinline__ double pick(const double (&v)[EPL], int cb) {
   return r;
 }
 
-// Block update and Grams on the matrix cores (32 and 64 columns, and 16
-// columns for binary32 blocks; binary64 16-column blocks keep the VALU
-// kernel above, which already streams at the copy rate).  A
+// Block update and Grams on the matrix cores (32 and 64 columns; at 16
+// columns binary32 blocks and the binary64 launches with Grams, while the
+// binary64 pure updates keep the VALU kernel above, measured faster).  A
 // row group of W = TPI / 16 waves takes 16 rows per step; wave w of it owns
 // output columns 16 w .. 16 w + 15 (a work-group of four waves holds 4 / W
 // row groups).  The update out = sum_b X_b C_b is a 16 x TPI by TPI x 16
@@ -2153,9 +2159,12 @@ void k_update_gram_mf(UGArgs<S> a) {
     double xo, ro;
   };
   // x_in and r_in are null when the launch carries no fold: the loads then
-  // read the first operand instead (at least 8 n bytes), and go unused
+  // read the first operand instead, and go unused
   const double* xsrc = fold ? a.x_in : reinterpret_cast<const double*>(src[0]);
   const double* rsrc = fold ? a.r_in : reinterpret_cast<const double*>(src[0]);
+  // without a fold, row rc reads the first 8 bytes of its own row of X[0]
+  // (loaded anyway): no extra traffic
+  const int64_t xstride = fold ? 1 : (int64_t)(TPI * sizeof(S) / 8);
   auto load_step = [&](int64_t st, Ld& d) {
     const int64_t r0 = st * (16 * RG) + 16 * rg + rq;
     for (int v = 0; v < 4; ++v) {
@@ -2167,8 +2176,8 @@ void k_update_gram_mf(UGArgs<S> a) {
     if constexpr (FOLDK) {
       const int64_t row = r0 + 4 * (m & 3);
       const int64_t rc = row < n ? row : n - 1;
-      d.xo = xsrc[rc];
-      d.ro = rsrc[rc];
+      d.xo = xsrc[rc * xstride];
+      d.ro = rsrc[rc * xstride];
     }
   };
   // a one-wave row group (16 columns) orders its own LDS accesses; wider
@@ -2823,7 +2832,8 @@ hipError_t launch_update_gram(int nu, int ng, bool ident0, bool write_out, int t
       hipLaunchKernelGGL((k_update_gram_mf<TPI, S, NU, NG, ID, WR, P0X>),                  \
                          dim3(grid * kCSGroups), dim3(kThreads), 0, st, a);                \
     else if constexpr ((TPI == 32 && ECG_MF32) ||                                         \
-                       (TPI == 16 && ECG_MF16F && sizeof(S) == 4))                          \
+                       (TPI == 16 && ECG_MF16F && sizeof(S) == 4) ||                        \
+                       (TPI == 16 && ECG_MF16D && sizeof(S) == 8 && NG > 0))                \
       hipLaunchKernelGGL((k_update_gram_mf<TPI, S, NU, NG, ID, WR, P0X>), dim3(grid),      \
                          dim3(kThreads), 0, st, a);                                        \
     else                                                                                   \
