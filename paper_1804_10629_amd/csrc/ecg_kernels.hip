@@ -1228,7 +1228,9 @@ __global__ ECG_SPMM_ATTR void k_spmm_wide(SpArgs<double, double> a) {
   if (step < sp.end) {
     load_rowptr(step, rp_cur);
     load_chunk(rp_cur, 0, h_cur);
-    load_rowptr(step + sp.stride, rp_nxt);   // rows past the end are clamped
+    // past the work-group's last step the current one is loaded again
+    // (cache hits; unused)
+    load_rowptr(step + sp.stride < sp.end ? step + sp.stride : step, rp_nxt);
   }
   for (; step < sp.end; step += sp.stride) {
     // next step's chunk and the row pointers after it: issued before this
@@ -1236,7 +1238,7 @@ __global__ ECG_SPMM_ATTR void k_spmm_wide(SpArgs<double, double> a) {
     Head h_nxt;
     RowPtr rp_nn;
     load_chunk(rp_nxt, 0, h_nxt);
-    load_rowptr(step + 2 * sp.stride, rp_nn);
+    load_rowptr(step + 2 * sp.stride < sp.end ? step + 2 * sp.stride : step, rp_nn);
     // Gram operands in the MFMA layout (lane: row rq + 4 k, column m)
     double z[4], pz[4], rv[4], okm[4];
     if constexpr (GRAMS) {
@@ -1387,13 +1389,15 @@ __global__ ECG_SPMM_ATTR void k_spmm_w32(SpArgs<double, double> a) {
   if (step < sp.end) {
     load_rowptr(step, rp_cur);
     load_chunk(rp_cur, 0, h_cur);
-    load_rowptr(step + sp.stride, rp_nxt);   // rows past the end are clamped
+    // past the work-group's last step the current one is loaded again
+    // (cache hits; unused)
+    load_rowptr(step + sp.stride < sp.end ? step + sp.stride : step, rp_nxt);
   }
   for (; step < sp.end; step += sp.stride) {
     Head h_nxt;
     RowPtr rp_nn;
     load_chunk(rp_nxt, 0, h_nxt);
-    load_rowptr(step + 2 * sp.stride, rp_nn);
+    load_rowptr(step + 2 * sp.stride < sp.end ? step + 2 * sp.stride : step, rp_nn);
     double z[RQ][EPL], pz[RQ][EPL], rv[RQ], okm[RQ];
     if constexpr (GRAMS) {
       for (int q = 0; q < RQ; ++q) {
@@ -1564,13 +1568,15 @@ __global__ ECG_SPMM_ATTR void k_spmm_w32f(SpArgs<float, float> a) {
   if (step < sp.end) {
     load_rowptr(step, rp_cur);
     load_chunk(rp_cur, 0, h_cur);
-    load_rowptr(step + sp.stride, rp_nxt);   // rows past the end are clamped
+    // past the work-group's last step the current one is loaded again
+    // (cache hits; unused)
+    load_rowptr(step + sp.stride < sp.end ? step + sp.stride : step, rp_nxt);
   }
   for (; step < sp.end; step += sp.stride) {
     Head h_nxt;
     RowPtr rp_nn;
     load_chunk(rp_nxt, 0, h_nxt);
-    load_rowptr(step + 2 * sp.stride, rp_nn);
+    load_rowptr(step + 2 * sp.stride < sp.end ? step + 2 * sp.stride : step, rp_nn);
     // Gram operands in the MFMA layout: row 4 k + rq of the step, column m + 16 e
     double z[4][EPL], pz[4][EPL], rv[4], okm[4];
     if constexpr (GRAMS) {
@@ -1743,13 +1749,13 @@ __global__ ECG_SPMM_ATTR void k_spmm_widef(SpArgs<float, float> a) {
   if (step < sp.end) {
     load_rowptr(step, rp_cur);
     load_chunk(rp_cur, 0, h_cur);
-    load_rowptr(step + sp.stride, rp_nxt);
+    load_rowptr(step + sp.stride < sp.end ? step + sp.stride : step, rp_nxt);
   }
   for (; step < sp.end; step += sp.stride) {
     Head h_nxt;
     RowPtr rp_nn;
     load_chunk(rp_nxt, 0, h_nxt);
-    load_rowptr(step + 2 * sp.stride, rp_nn);
+    load_rowptr(step + 2 * sp.stride < sp.end ? step + 2 * sp.stride : step, rp_nn);
     constexpr int NK = 4 * RQ;                   // 4-row groups of the step
     double z[NK], pz[NK], rv[NK], okm[NK];
     if constexpr (GRAMS) {
@@ -2194,8 +2200,9 @@ void k_update_gram_mf(UGArgs<S> a) {
     Ld ldc;
     if constexpr (PF) {
       ldc = nx;
-      // past the last step the rows are clamped and the values unused
-      load_step(step + sp.stride, nx);
+      // past the work-group's last step the current one is loaded again
+      // (cache hits; unused)
+      load_step(step + sp.stride < sp.end ? step + sp.stride : step, nx);
     } else {
       load_step(step, ldc);
     }
