@@ -217,3 +217,23 @@ def test_mixed_precision_wide_blocks(E, m, t, s, parts):
     assert _rel(x, ref.x) <= 1e-5
     m32 = O.sstep_srecg(A, dom, t, s, p.b, tol=1e-8, basis_dtype=np.float32, inner_tol=1e-4)
     assert abs(info.iters - m32.iters) <= max(3, 0.1 * m32.iters)
+
+
+@pytest.mark.parametrize("m,t,s,parts", [(40, 8, 3, (2, 4, 1)), (48, 32, 2, (4, 8, 1)),
+                                         (64, 64, 2, (8, 8, 1))])
+@pytest.mark.parametrize("grid", [1, 7, 2048])
+def test_custom_grid_matches_default(E, m, t, s, parts, grid):
+    # launch grids that are not a multiple of the 8 XCDs (plain striding),
+    # a single work-group, and more work-groups than the default: the same
+    # iterates up to the order of the work-group sums
+    p = P.poisson2d(m, t=t, parts=parts, seed=m + 5)
+    A = p.scipy()
+    ref, _ = _setup(E, p, t, s, parts)
+    xr, ir = ref.solve(p.b, tol=1e-8, maxit=2000)
+    sol, _ = _setup(E, p, t, s, parts, grid=grid)
+    x, info = sol.solve(p.b, tol=1e-8, maxit=2000)
+    assert info.status == E.OK and abs(info.iters - ir.iters) <= 1
+    assert _rel(x.cpu().numpy(), xr.cpu().numpy()) <= 1e-9
+    assert np.linalg.norm(p.b - A @ x.cpu().numpy()) / np.linalg.norm(p.b) <= 1e-8
+    ref.close()
+    sol.close()
