@@ -49,7 +49,7 @@ extern "C" {
 #define ECG_EINVAL     -1  /* invalid argument (message: ecg_last_error) */
 #define ECG_ENOMEM     -2  /* device allocation failed */
 #define ECG_EDEVICE    -3  /* HIP runtime error or no usable gfx950 device */
-#define ECG_ENOTSUP    -4  /* valid request this build does not support */
+#define ECG_ENOTSUP    -4  /* valid request the library does not support */
 
 /* ---- options ----------------------------------------------------------- */
 enum ecg_variant   { ECG_SRECG = 0,   /* s-step SRE-CG: each block against the
