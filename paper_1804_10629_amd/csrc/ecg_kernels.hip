@@ -308,14 +308,27 @@ __device__ __forceinline__ void mat_to_lds(const double* src, double* dst, int c
 // one step issue back to back.
 template <int TPI, bool TRANS>
 __device__ __forceinline__ void col_mul(const double* A, const double (&x)[TPI], double (&y)[TPI]) {
+  // column k+1 of op(A) is read while column k's FMAs run (two columns in
+  // registers at a time)
+  double cur[TPI], nxt[TPI];
 #pragma unroll
-  for (int i = 0; i < TPI; ++i) y[i] = 0.0;
+  for (int i = 0; i < TPI; ++i) {
+    y[i] = 0.0;
+    cur[i] = TRANS ? A[i] : A[i * TPI];
+  }
 #pragma unroll
   for (int k = 0; k < TPI; ++k) {
-    asm volatile("" ::: "memory");   // one column of op(A) in flight at a time
+    if (k + 1 < TPI) {
 #pragma unroll
-    for (int i = 0; i < TPI; ++i)
-      y[i] = __builtin_fma(TRANS ? A[k * TPI + i] : A[i * TPI + k], x[k], y[i]);
+      for (int i = 0; i < TPI; ++i) nxt[i] = TRANS ? A[(k + 1) * TPI + i] : A[i * TPI + k + 1];
+    }
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < TPI; ++i) y[i] = __builtin_fma(cur[i], x[k], y[i]);
+    if (k + 1 < TPI) {
+#pragma unroll
+      for (int i = 0; i < TPI; ++i) cur[i] = nxt[i];
+    }
   }
 }
 
@@ -365,6 +378,10 @@ __device__ void w_chol(double (&g)[TPI], int t, int* bad) {
 template <int TPI>
 __device__ void w_trinv(const double* R, int t, double (&x)[TPI]) {
   const int c = threadIdx.x & 63;
+  // reciprocals of the pivots first: independent divisions, not a chain
+  double rd[TPI];
+#pragma unroll
+  for (int k = 0; k < TPI; ++k) rd[k] = k < t ? 1.0 / R[k * TPI + k] : 0.0;
 #pragma unroll
   for (int i = 0; i < TPI; ++i) x[i] = (i == c) ? 1.0 : 0.0;
 #pragma unroll
@@ -374,7 +391,7 @@ __device__ void w_trinv(const double* R, int t, double (&x)[TPI]) {
       continue;
     }
     asm volatile("" ::: "memory");
-    x[k] = c < t ? x[k] / R[k * TPI + k] : 0.0;
+    x[k] = c < t ? x[k] * rd[k] : 0.0;
 #pragma unroll
     for (int i = 0; i < k; ++i) x[i] = __builtin_fma(-R[i * TPI + k], x[k], x[i]);
   }
@@ -516,31 +533,34 @@ __device__ void tail_pre(double* sums, double* tmp, const TailArgs& ta) {
 // padding.
 template <int TPI>
 __device__ void b_chol(double* G, int t, int* bad) {
+  // Right-looking, one barrier per pivot: step j updates the trailing upper
+  // triangle with the unscaled row j over the pivot (G[i][c] -= G[j][i]
+  // G[j][c] / G[j][j]); the rows are scaled by their pivots' square roots
+  // in one pass at the end.  Every thread derives the same pivot value.
   const int tid = threadIdx.x;
   for (int j = 0; j < t; ++j) {
-    if (tid == 0) {
-      const double piv = G[j * TPI + j];
-      if (!(piv > 0.0) || !isfinite(piv)) {
-        *bad = 1;
-        G[j * TPI + j] = 1.0;
-      } else {
-        G[j * TPI + j] = sqrt(piv);
-      }
-    }
-    __syncthreads();
-    const double d = G[j * TPI + j];
-    for (int c = j + 1 + tid; c < t; c += blockDim.x) G[j * TPI + c] /= d;
-    __syncthreads();
+    double piv = G[j * TPI + j];
+    const bool okp = piv > 0.0 && isfinite(piv);
+    if (!okp) piv = 1.0;
+    if (!okp && tid == 0) *bad = 1;
+    const double inv = 1.0 / piv;
     const int w = t - j - 1;
     for (int idx = tid; idx < w * w; idx += blockDim.x) {
       const int i = j + 1 + idx / w, c = j + 1 + idx % w;
-      if (i <= c) G[i * TPI + c] -= G[j * TPI + i] * G[j * TPI + c];
+      if (i <= c) G[i * TPI + c] -= G[j * TPI + i] * G[j * TPI + c] * inv;
     }
     __syncthreads();
   }
   for (int idx = tid; idx < TPI * TPI; idx += blockDim.x) {
     const int i = idx / TPI, c = idx % TPI;
-    if (i > c || i >= t || c >= t) G[idx] = 0.0;
+    double v = 0.0;
+    if (i < t && c < t && i <= c) {
+      double piv = G[i * TPI + i];
+      if (!(piv > 0.0 && isfinite(piv))) piv = 1.0;
+      const double d = sqrt(piv);
+      v = (i == c) ? d : G[idx] / d;
+    }
+    G[idx] = v;
   }
   __syncthreads();
 }
@@ -561,6 +581,28 @@ __device__ void b_trinv(double* R, int t, double* tmp) {
     for (int i = tid; i < j; i += blockDim.x) R[i * TPI + j] = -tmp[i] * inv;
     if (tid == 0) R[j * TPI + j] = inv;
     __syncthreads();
+  }
+}
+
+// R <- R^{-1}: at 32 columns lane c of wave 0 forms column c by back
+// substitution (w_trinv, no barriers) into tmp, then the work-group copies
+// it back; at 64 columns (a column per lane would need 128 registers more)
+// the barrier-per-column form b_trinv.
+template <int TPI>
+__device__ void b_inverse(double* R, int t, double* tmp) {
+  if constexpr (TPI == 32) {
+    if (threadIdx.x < TPI) {
+      double x[TPI];
+      w_trinv<TPI>(R, t, x);
+      const int c = threadIdx.x;
+#pragma unroll
+      for (int i = 0; i < TPI; ++i) tmp[i * TPI + c] = x[i];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < TPI * TPI; idx += blockDim.x) R[idx] = tmp[idx];
+    __syncthreads();
+  } else {
+    b_trinv<TPI>(R, t, tmp);
   }
 }
 
@@ -605,7 +647,7 @@ __device__ void btail_spmm(double* sums, double* tmp, const TailArgs& ta) {
   if (tid == 0) s_bad = 0;
   __syncthreads();
   b_chol<TPI>(G, t, &s_bad);
-  b_trinv<TPI>(G, t, tmp);           // G now holds R^{-1}
+  b_inverse<TPI>(G, t, tmp);         // G now holds R^{-1}
   for (int idx = tid; idx < T2; idx += blockDim.x) {
     ta.rinv_cur[idx] = G[idx];
     ta.cnext[idx] = G[idx];                      // C0
@@ -683,7 +725,7 @@ __device__ void btail_pre(double* sums, double* tmp, const TailArgs& ta) {
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
   b_chol<TPI>(sums, ta.t, &s_bad);
-  b_trinv<TPI>(sums, ta.t, tmp);
+  b_inverse<TPI>(sums, ta.t, tmp);
   for (int idx = threadIdx.x; idx < TPI * TPI; idx += blockDim.x) ta.coef_out[0][idx] = sums[idx];
   if (threadIdx.x == 0 && s_bad && ta.status->breakdown == 0) {
     ta.status->breakdown = 1;
