@@ -87,7 +87,11 @@ typedef struct ecg_opts {
   void*   hip_stream;     /* hipStream_t to run on; NULL = null stream */
   int32_t collect_stats;  /* 1: time every kernel with HIP events (ecg_last_stats) */
   int32_t grid;           /* work-groups per streaming kernel; 0 = automatic */
-  int32_t reserved[6];    /* must be zero */
+  int32_t progress_every; /* > 0: print the iteration count, rho_k / rho_0 and
+                             the elapsed host time to stderr after every this
+                             many s-step iterations and at every restart
+                             (default 0: silent) */
+  int32_t reserved[5];    /* must be zero */
 } ecg_opts;
 
 /* Fill *o with the defaults above. */
@@ -173,21 +177,36 @@ int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const int32_t* co
               const ecg_opts* opts);
 
 /*
- * Solve A x = b.  x holds x0 on entry and the solution on exit.  The
- * iteration follows the s-step algorithms of Section 3.1: it stops when the
- * recursive residual norm rho_k <= tol * rho_0 (rho_0 = ||b - A x0||), then
- * checks the true residual b - A x and, if that is above tol * rho_0,
- * restarts from x with r = b - A x (at most opts.max_restarts times).
- * maxit bounds the s-step iterations executed (restarts included).
- * reshist (may be NULL) receives rho_0, then rho_k after every iteration and
- * the true residual norm at every restart, at most reshist_cap values;
- * res (may be NULL) receives counts and norms.
- * Returns ECG_OK, ECG_MAXIT, ECG_BREAKDOWN or ECG_STAGNATED, or ECG_EINVAL
- * (NULL c/b/x; tol <= 0 or not finite; maxit < 0; reshist_cap < 0; a
- * non-finite entry in b or x0), ECG_EDEVICE.
+ * Solve A x = b (Section 3.1: the s-step algorithms take A, b, x0, the
+ * tolerance, s and the iteration bound k_max and return x).  x holds x0 on
+ * entry and the solution on exit.  The iteration stops when the recursive
+ * residual norm rho_k <= tol * rho_0 (rho_0 = ||b - A x0||; the stopping test
+ * of the s-step algorithms), then checks the true residual b - A x and, if
+ * that is above tol * rho_0, restarts from x with r = b - A x (at most
+ * opts.max_restarts times).  maxit bounds the s-step iterations executed
+ * (restarts included).
+ *   iters (may be NULL): s-step iterations executed.
+ *   reshist (may be NULL): caller buffer of at least
+ *     2 * maxit + opts.max_restarts + 2 doubles; receives rho_0, then rho_k
+ *     after every iteration and the true residual norm at every restart.
+ *   reshist_len (may be NULL): number of values written to reshist.
+ *   true_relres (may be NULL): ||b - A x||_2 / rho_0 at exit, in binary64.
+ * Returns ECG_OK, ECG_MAXIT, ECG_BREAKDOWN (x = last completed iterate) or
+ * ECG_STAGNATED, or ECG_EINVAL (NULL c/b/x; tol <= 0 or not finite;
+ * maxit < 0; a non-finite entry in b or x0), ECG_EDEVICE.  Synchronous on
+ * opts.hip_stream.
  */
 int ecg_solve(ecg_ctx* c, const double* b, double* x, double tol, int32_t maxit,
-              double* reshist, int32_t reshist_cap, ecg_result* res);
+              int32_t* iters, double* reshist, int32_t* reshist_len, double* true_relres);
+
+/*
+ * ecg_solve with every count of the solve: reshist (may be NULL) receives at
+ * most reshist_cap values of the history above; res (may be NULL) receives
+ * the counts and norms of ecg_result (res->status = the return value, also
+ * on errors).  Errors as ecg_solve, plus ECG_EINVAL for reshist_cap < 0.
+ */
+int ecg_solve_ex(ecg_ctx* c, const double* b, double* x, double tol, int32_t maxit,
+                 double* reshist, int32_t reshist_cap, ecg_result* res);
 
 /*
  * Gradient of a loss through x = A^{-1} b with respect to the stored

@@ -35,7 +35,7 @@ import scipy.sparse as sp
 __all__ = [
     "OK", "MAXIT", "BREAKDOWN", "STAGNATED",
     "csr", "partition_grid", "split_T", "chol_upper", "cgs2_a", "a_cholqr",
-    "pre_cholqr", "cg", "srecg", "sstep_srecg", "SolveResult",
+    "pre_cholqr", "cg", "srecg", "sstep_srecg", "SolveResult", "basis_matrix", "true_residual",
     "dense_cholesky_solve", "sddmm", "dense_gradient", "Breakdown",
 ]
 
@@ -187,19 +187,24 @@ class _BlockStore:
         return self.W[:, :self.m], self.AW[:, :self.m]
 
 
-def a_cholqr(Ab: sp.csr_matrix, Z: np.ndarray, dtype=np.float64):
+def a_cholqr(Ab: sp.csr_matrix, Z: np.ndarray, dtype=np.float64, trace=None):
     """A-CholQR: G = Z^t A Z = R^t R, W = Z R^{-1}, A W = (A Z) R^{-1}.
-    READING: G is formed from its upper triangle (i <= j) and mirrored."""
+    READING: G is formed from its upper triangle (i <= j) and mirrored.
+    `trace` (a dict, optional) receives Z, A Z, G and R."""
     AZ = _spmm(Ab, Z, dtype)
     G = _f64(Z).T @ _f64(AZ)
     G = np.triu(G) + np.triu(G, 1).T
+    if trace is not None:
+        trace.update(Z=Z, AZ=AZ, G=G)
     R = chol_upper(G)
     W = _store(sla.solve_triangular(R, _f64(Z).T, trans="T", lower=False).T, dtype)
     AW = _store(sla.solve_triangular(R, _f64(AZ).T, trans="T", lower=False).T, dtype)
+    if trace is not None:
+        trace.update(R=R, W=W, AW=AW)
     return W, AW, R
 
 
-def pre_cholqr(Ab: sp.csr_matrix, Z: np.ndarray, dtype=np.float64):
+def pre_cholqr(Ab: sp.csr_matrix, Z: np.ndarray, dtype=np.float64, trace=None):
     """Pre-CholQR: a Euclidean CholQR of Z (Z^t Z = Re^t Re, Z <- Z Re^{-1})
     followed by A-CholQR of the result."""
     Zd = _f64(Z)
@@ -207,7 +212,25 @@ def pre_cholqr(Ab: sp.csr_matrix, Z: np.ndarray, dtype=np.float64):
     Ge = np.triu(Ge) + np.triu(Ge, 1).T
     Re = chol_upper(Ge)
     Z = _store(sla.solve_triangular(Re, Zd.T, trans="T", lower=False).T, dtype)
-    return a_cholqr(Ab, Z, dtype)
+    if trace is None:
+        return a_cholqr(Ab, Z, dtype)
+    trace["Z_pre"] = Zd
+    return a_cholqr(Ab, Z, dtype, trace=trace)
+
+
+def basis_matrix(A: sp.csr_matrix, dtype) -> sp.csr_matrix:
+    """The matrix the basis is built with: A itself, or in the binary32
+    precision form A with its values rounded to binary32 (held as float64,
+    so that products with binary32 blocks are exact before the sum)."""
+    if dtype == np.float64:
+        return A
+    return csr(A.indptr, A.indices, A.data.astype(np.float32).astype(np.float64), A.shape[0])
+
+
+def true_residual(A: sp.csr_matrix, b: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """b - A x with the binary64 matrix (initial residual and every residual
+    replacement, in both precision forms)."""
+    return b - A @ x
 
 
 # ---------------------------------------------------------------------------
@@ -312,7 +335,8 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
                 x0=None, tol=1e-8, maxit=100000, *, variant="srecg",
                 orth="acholqr", aimage="stored", basis_dtype=np.float64,
                 inner_tol=0.0, max_restarts=20, q_cap_blocks=0,
-                record=False, stop_after_blocks: Optional[int] = None) -> SolveResult:
+                record=False, stop_after_blocks: Optional[int] = None,
+                trace: Optional[list] = None) -> SolveResult:
     """s-step SRE-CG (variant='srecg') / s-step SRE-CG2 ('srecg2') / s-step
     MSDO-CG ('msdo', Section 3.2, algorithm "s-step MSDO-CG").
 
@@ -346,17 +370,19 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
       * SRE-CG2 and MSDO-CG keep all blocks since the last restart; when
         q_cap_blocks > 0 and another s blocks would exceed it, the solve
         restarts from x.
+
+    `trace` (a list, optional) receives one dict per block (the CGS2 output
+    Z, A Z, the Gram G, R, W and A W) and one per true-residual check (x
+    and its residual norm), for the precision pins.
     """
     if s < 1 or t < 1:
         raise ValueError("s and t must be >= 1")
     if variant not in ("srecg", "srecg2", "msdo"):
         raise ValueError("variant must be 'srecg', 'srecg2' or 'msdo'")
     dtype = np.dtype(basis_dtype).type
-    Ab = A if dtype == np.float64 else csr(A.indptr, A.indices,
-                                           A.data.astype(np.float32).astype(np.float64),
-                                           A.shape[0])
+    Ab = basis_matrix(A, dtype)
     x = np.zeros_like(b) if x0 is None else x0.astype(np.float64).copy()
-    r = b - A @ x
+    r = true_residual(A, b, x)
     rho0 = float(np.linalg.norm(r))
     hist = [rho0]
     res = SolveResult(x, 0, hist, OK)
@@ -384,7 +410,7 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
         while rho > thr and k < maxit:
             if (variant != "srecg" and q_cap_blocks and not fresh_start
                     and len(blocks) + s > q_cap_blocks):
-                r = b - A @ x
+                r = true_residual(A, b, x)
                 rho = float(np.linalg.norm(r))
                 hist.append(rho)
                 restarts += 1
@@ -403,7 +429,12 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
                     else:
                         Z = _spmm(Ab, blocks.last()[0], dtype)
                     Z = cgs2_a(Z, *blocks.all(), dtype)
-                    W, AW, _ = orthonormalize(Ab, Z, dtype)
+                    if trace is None:
+                        W, AW, _ = orthonormalize(Ab, Z, dtype)
+                    else:
+                        tr = {"block": nblocks + 1, "iteration": k + 1}
+                        trace.append(tr)
+                        W, AW, _ = orthonormalize(Ab, Z, dtype, trace=tr)
                     blocks.add(W, AW)
                     V.append(W)
                     AV.append(AW)
@@ -434,8 +465,10 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
         if rho > thr:             # iteration budget exhausted
             status = MAXIT
             break
-        rt = b - A @ x
+        rt = true_residual(A, b, x)
         tau = float(np.linalg.norm(rt))
+        if trace is not None:
+            trace.append({"replacement": restarts + 1, "x": x.copy(), "tau": tau})
         if tau <= thr_final:
             status = OK
             break

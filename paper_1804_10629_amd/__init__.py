@@ -50,7 +50,8 @@ class _Opts(ctypes.Structure):
         ("inner_tol", ctypes.c_double), ("max_restarts", ctypes.c_int32),
         ("q_cap_blocks", ctypes.c_int32), ("ws_cap_bytes", ctypes.c_int64),
         ("hip_stream", ctypes.c_void_p), ("collect_stats", ctypes.c_int32),
-        ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6),
+        ("grid", ctypes.c_int32), ("progress_every", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -82,8 +83,10 @@ _SIGS = {
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "ecg_setup": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int64, _P, _P, _P, _P,
                                  ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_Opts)]),
-    "ecg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int32, _P,
-                                 ctypes.c_int32, ctypes.POINTER(_Result)]),
+    "ecg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int32, _P, _P, _P,
+                                 _P]),
+    "ecg_solve_ex": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int32, _P,
+                                    ctypes.c_int32, ctypes.POINTER(_Result)]),
     "ecg_sddmm": (ctypes.c_int, [_P, _P, _P, _P]),
     "ecg_spmm": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
     "ecg_tsplit": (ctypes.c_int, [_P, _P, _P]),
@@ -201,7 +204,8 @@ class Solver:
     def __init__(self, rowptr, colind, vals, partition, t: int, s: int, *,
                  variant: int = SRECG, orth: int = ACHOLQR, precision: int = FP64,
                  inner_tol: float = 1e-4, max_restarts: int = 20, q_cap_blocks: int = 0,
-                 ws_cap_bytes: int = 0, collect_stats: bool = False, grid: int = 0):
+                 ws_cap_bytes: int = 0, collect_stats: bool = False, grid: int = 0,
+                 progress_every: int = 0):
         torch = _torch()
         self._ctx = _P()
         o = _Opts()
@@ -210,6 +214,7 @@ class Solver:
         o.device_ptrs = 1
         o.inner_tol, o.max_restarts, o.q_cap_blocks = inner_tol, max_restarts, q_cap_blocks
         o.ws_cap_bytes, o.collect_stats, o.grid = ws_cap_bytes, int(collect_stats), grid
+        o.progress_every = progress_every
         o.hip_stream = _stream_ptr()
         self.opts = o
         rp = _dev_tensor(rowptr, torch.int32)
@@ -246,7 +251,7 @@ class Solver:
         cap = 2 * maxit + self.opts.max_restarts + 4
         hist = np.zeros(cap, dtype=np.float64)
         res = _Result()
-        code = lib.ecg_solve(self._ctx, bd.data_ptr(), x.data_ptr(), float(tol), int(maxit),
+        code = lib.ecg_solve_ex(self._ctx, bd.data_ptr(), x.data_ptr(), float(tol), int(maxit),
                              hist.ctypes.data, cap, ctypes.byref(res))
         _check(code)
         info = SolveInfo(code, res.iters, res.restarts, res.blocks, res.rho0, res.relres,

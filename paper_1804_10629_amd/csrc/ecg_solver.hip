@@ -20,6 +20,8 @@
 #include "ecg_kernels.h"
 
 #include <algorithm>
+#include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -319,7 +321,7 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   ecg_opts o;
   if (opts) o = *opts;
   else ecg_opts_default(&o);
-  for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < 5; ++i)
     if (o.reserved[i] != 0) return fail(ECG_EINVAL, "reserved option fields must be zero");
   if (!rowptr || !colind || !vals || !partition) return fail(ECG_EINVAL, "NULL array argument");
   if (n <= 0) return fail(ECG_EINVAL, "n must be positive");
@@ -333,7 +335,8 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   if (o.precision != ECG_FP64 && o.precision != ECG_MIXED) return fail(ECG_EINVAL, "bad precision");
   if (o.device_ptrs != 0 && o.device_ptrs != 1) return fail(ECG_EINVAL, "bad device_ptrs");
   if (!(o.inner_tol >= 0.0 && o.inner_tol < 1.0)) return fail(ECG_EINVAL, "inner_tol must be in [0, 1)");
-  if (o.max_restarts < 0 || o.q_cap_blocks < 0 || o.ws_cap_bytes < 0 || o.grid < 0)
+  if (o.max_restarts < 0 || o.q_cap_blocks < 0 || o.ws_cap_bytes < 0 || o.grid < 0 ||
+      o.progress_every < 0)
     return fail(ECG_EINVAL, "negative option");
   if (o.variant != ECG_SRECG && o.q_cap_blocks > 0 && o.q_cap_blocks < s)
     return fail(ECG_EINVAL, "q_cap_blocks must be 0 or at least s");
@@ -873,12 +876,24 @@ struct Engine {
       if (hist && hl < cap) hist[hl] = v;
       ++hl;
     };
+    const auto t_start = std::chrono::steady_clock::now();
+    double rho0_log = 0.0;
+    // opt-in progress line on stderr (long solves)
+    auto progress = [&](const char* what, int k, int restarts, double rho) {
+      if (c->o.progress_every <= 0 || rho0_log <= 0.0) return;
+      const double ms = std::chrono::duration<double, std::milli>(
+                            std::chrono::steady_clock::now() - t_start).count();
+      std::fprintf(stderr, "ecg: %s iter %d restarts %d rho/rho0 %.3e  %.1f ms\n", what, k,
+                   restarts, rho / rho0_log, ms);
+      std::fflush(stderr);
+    };
     DevStatus h{};
     HIP_TRY(hipMemsetAsync(c->status, 0, sizeof(DevStatus), c->st));
     if ((rc = resid(1))) return rc;
     if ((rc = read_status(&h))) return rc;
     const double rho0 = h.rho_true;
     res->rho0 = rho0;
+    rho0_log = rho0;
     if (!std::isfinite(rho0)) return fail(ECG_EINVAL, "b or x0 contains a non-finite value");
     push(rho0);
     if (rho0 == 0.0) {
@@ -912,6 +927,7 @@ struct Engine {
           rho = h.rho_true;
           push(rho);
           ++restarts;
+          progress("block-cap restart at", k, restarts, rho);
           rho_restart = rho;
           m = 0;
           slot_of[0] = slot_of[1] = slot_of[2] = -1;
@@ -950,6 +966,8 @@ struct Engine {
         rho = h.rho;
         ++k;
         push(rho);
+        if (c->o.progress_every > 0 && k % c->o.progress_every == 0)
+          progress("", k, restarts, rho);
         c->last_nb = c->s;
         for (int i = 0; i < c->s; ++i) c->last_slots[i] = slots[i];
         have_basis = true;
@@ -975,6 +993,7 @@ struct Engine {
       rho = tau;
       push(tau);
       ++restarts;
+      progress("true-residual restart at", k, restarts, tau);
       rho_restart = tau;
       m = 0;
       slot_of[0] = slot_of[1] = slot_of[2] = -1;
@@ -989,6 +1008,7 @@ struct Engine {
     res->relres = rho / rho0;
     res->true_relres = h.rho_true / rho0;
     res->hist_len = std::min(hl, cap);
+    progress("done at", k, restarts, h.rho_true);
     return status;
   }
 };
@@ -1005,15 +1025,13 @@ int run_tpi(ecg_ctx* c, double tol, int maxit, double* hist, int cap, ecg_result
 
 }  // namespace
 
-extern "C" int ecg_solve(ecg_ctx* c, const double* b, double* x, double tol, int32_t maxit,
-                         double* reshist, int32_t reshist_cap, ecg_result* res) {
+namespace {
+int solve_impl(ecg_ctx* c, const double* b, double* x, double tol, int32_t maxit,
+               double* reshist, int32_t reshist_cap, ecg_result* res) {
   if (!c || !b || !x) return fail(ECG_EINVAL, "NULL argument");
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(ECG_EINVAL, "tol must be positive and finite");
   if (maxit < 0) return fail(ECG_EINVAL, "maxit must be >= 0");
   if (reshist_cap < 0) return fail(ECG_EINVAL, "reshist_cap must be >= 0");
-  ecg_result tmp{};
-  if (!res) res = &tmp;
-  std::memset(res, 0, sizeof(*res));
   std::memset(&c->stats, 0, sizeof(c->stats));
   c->last_nb = 0;
   const bool dev = c->o.device_ptrs == 1;
@@ -1028,14 +1046,48 @@ extern "C" int ecg_solve(ecg_ctx* c, const double* b, double* x, double tol, int
     case 32: st = run_tpi<32>(c, tol, maxit, reshist, reshist_cap, res); break;
     default: st = run_tpi<64>(c, tol, maxit, reshist, reshist_cap, res); break;
   }
-  if (st < 0) return st;
+  if (st < 0) {
+    // a failed solve leaves no timings behind for the next one
+    (void)hipStreamSynchronize(c->st);
+    c->flush_timing();
+    std::memset(&c->stats, 0, sizeof(c->stats));
+    return st;
+  }
   HIP_TRY(hipEventRecord(c->ev_solve1, c->st));
   HIP_TRY(hipMemcpyAsync(x, c->x, sizeof(double) * c->n, outk, c->st));
   HIP_TRY(hipStreamSynchronize(c->st));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, c->ev_solve0, c->ev_solve1));
   res->solve_ms = ms;
+  return st;
+}
+}  // namespace
+
+extern "C" int ecg_solve_ex(ecg_ctx* c, const double* b, double* x, double tol, int32_t maxit,
+                            double* reshist, int32_t reshist_cap, ecg_result* res) {
+  ecg_result tmp{};
+  if (!res) res = &tmp;
+  std::memset(res, 0, sizeof(*res));
+  const int st = solve_impl(c, b, x, tol, maxit, reshist, reshist_cap, res);
   res->status = st;
+  return st;
+}
+
+extern "C" int ecg_solve(ecg_ctx* c, const double* b, double* x, double tol, int32_t maxit,
+                         int32_t* iters, double* reshist, int32_t* reshist_len,
+                         double* true_relres) {
+  ecg_result res{};
+  int cap = 0;
+  if (reshist) {
+    // rho_0, one value per iteration, one per residual replacement and one
+    // per block-cap restart (at most one per iteration)
+    const int64_t want = c ? 2 * (int64_t)maxit + c->o.max_restarts + 2 : 0;
+    cap = (int)std::min<int64_t>(want, INT32_MAX);
+  }
+  const int st = solve_impl(c, b, x, tol, maxit, reshist, cap, &res);
+  if (iters) *iters = res.iters;
+  if (reshist_len) *reshist_len = res.hist_len;
+  if (true_relres) *true_relres = res.true_relres;
   return st;
 }
 

@@ -107,3 +107,62 @@ def read_msdo_table():
             v = [int(x) for x in line.split()]
             out[v[0]] = (v[1], v[2:])
     return out
+
+
+# ---------------------------------------------------------------------------
+# The binary32-basis precision form
+# ---------------------------------------------------------------------------
+
+def _blocks(trace):
+    return [tr for tr in trace if "AZ" in tr]
+
+
+def binary32_representability_violation(trace) -> int:
+    """Number of entries of the recorded blocks (the CGS2 output Z handed to
+    A-CholQR, A Z, W and A W) that are not binary32 values: in the precision
+    form every stored block is a binary32 block."""
+    bad = 0
+    for tr in _blocks(trace):
+        for key in ("Z", "AZ", "W", "AW"):
+            v = np.asarray(tr[key], dtype=np.float64)
+            bad += int(np.count_nonzero(v.astype(np.float32).astype(np.float64) != v))
+    return bad
+
+
+def basis_product_rounding_violation(trace, A32_dense) -> float:
+    """max |A Z - P| / ulp32(P) over the recorded blocks, where P is the
+    product of the binary32-rounded matrix with Z formed as a dense product
+    (products of binary32 values are exact in binary64; the binary64 sum is
+    far more accurate than a binary32 ulp).  A Z rounded to nearest from
+    that product gives at most 0.5."""
+    worst = 0.0
+    for tr in _blocks(trace):
+        P = A32_dense @ np.asarray(tr["Z"], dtype=np.float64)
+        got = np.asarray(tr["AZ"], dtype=np.float64)
+        ulp = np.spacing(np.abs(P).astype(np.float32)).astype(np.float64)
+        worst = max(worst, float((np.abs(got - P) / ulp).max()))
+    return worst
+
+
+def gram_accuracy_violation(trace) -> float:
+    """max over the recorded Grams G = Z^t (A Z) of |G - G_exact| in units of
+    the binary64 summation bound n * 2^-53 * (|Z|^t |A Z|), with G_exact the
+    correctly rounded exact sum (math.fsum of products that are exact, both
+    factors being binary32 values).  A Gram accumulated in binary64 gives at
+    most 1; one accumulated in binary32 gives about 2^29 / n."""
+    worst = 0.0
+    for tr in _blocks(trace):
+        Z = np.asarray(tr["Z"], dtype=np.float64)
+        AZ = np.asarray(tr["AZ"], dtype=np.float64)
+        G = np.asarray(tr["G"], dtype=np.float64)
+        n, t = Z.shape
+        absb = np.abs(Z).T @ np.abs(AZ)
+        for i in range(t):
+            for j in range(i, t):
+                exact = math.fsum(Z[:, i] * AZ[:, j])
+                bound = n * 2.0 ** -53 * absb[i, j]
+                if bound > 0:
+                    worst = max(worst, abs(G[i, j] - exact) / bound)
+                elif G[i, j] != exact:
+                    worst = float("inf")
+    return worst

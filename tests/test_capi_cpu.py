@@ -45,7 +45,7 @@ def test_opts_default():
     E.lib.ecg_opts_default(ctypes.byref(o))
     assert (o.variant, o.orth, o.precision, o.device_ptrs) == (0, 0, 0, 0)
     assert o.inner_tol == 1e-4 and o.max_restarts == 20 and o.grid == 0
-    assert list(o.reserved) == [0] * 6
+    assert list(o.reserved) == [0] * 5
 
 
 def _setup(n, rowptr, colind, vals, part, t, s, **kw):
@@ -102,7 +102,7 @@ def test_setup_rejects(small, case):
     elif case == "nan_value":
         va[10] = np.nan
     elif case == "reserved":
-        kw = {"reserved": (ctypes.c_int32 * 6)(0, 0, 1, 0, 0, 0)}
+        kw = {"reserved": (ctypes.c_int32 * 5)(0, 0, 1, 0, 0)}
     elif case == "variant":
         kw = {"variant": 7}
     elif case == "inner_tol":
@@ -124,7 +124,8 @@ def test_setup_without_gpu_reports_device_error(small):
 
 def test_null_arguments():
     assert E.lib.ecg_setup(None, 1, None, None, None, None, 1, 1, None) == E.EINVAL
-    assert E.lib.ecg_solve(None, None, None, 1e-8, 10, None, 0, None) == E.EINVAL
+    assert E.lib.ecg_solve(None, None, None, 1e-8, 10, None, None, None, None) == E.EINVAL
+    assert E.lib.ecg_solve_ex(None, None, None, 1e-8, 10, None, 0, None) == E.EINVAL
     assert E.lib.ecg_sddmm(None, None, None, None) == E.EINVAL
     assert E.lib.ecg_spmm(None, None, None, 4) == E.EINVAL
     assert E.lib.ecg_tsplit(None, None, None) == E.EINVAL

@@ -114,7 +114,7 @@ def test_heterogeneous_3d_parity(E):
     runs = oracle_ensemble(A, dom, 16, 4, p.b)
     x, info = sol.solve(p.b, tol=1e-8, maxit=2000)
     assert info.status == E.OK and info.true_relres <= 1e-8
-    print(check_parity(info.iters, x.cpu().numpy(), runs))
+    print(check_parity(info.iters, x.cpu().numpy(), runs, A))
 
 
 def test_bitwise_reproducible(E, c1):

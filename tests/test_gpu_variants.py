@@ -143,7 +143,7 @@ def test_srecg2_heterogeneous_3d(E):
     sol = E.Solver(p.rowptr, p.colind, p.vals, dom, 16, 4, variant=E.SRECG2)
     x, info = sol.solve(p.b, tol=1e-8, maxit=2000)
     assert info.status == E.OK and info.true_relres <= 1e-8
-    print(check_parity(info.iters, x.cpu().numpy(), runs))
+    print(check_parity(info.iters, x.cpu().numpy(), runs, A))
     sol.close()
 
 

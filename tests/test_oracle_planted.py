@@ -163,3 +163,88 @@ def test_skipped_second_block_update_changes_iteration_count(c1, monkeypatch):
         monkeypatch.setattr(E.np, "hstack", orig_hstack)
     want = pinlib.read_poisson_table()[("sre-cg", 8)][pinlib.SVALS.index(4)]
     assert abs(it - want) > max(2, 0.10 * want)
+
+
+# ---------------------------------------------------------------------------
+# The binary32-basis precision form: each plausible slip fails a pin
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def lu_small():
+    shape = (30, 30, 1)
+    p = P.make_problem("lu", shape, P.kappa_loguniform(shape, 4, -2, 2), seed=4, t=4, s=2,
+                       parts=(2, 2, 1))
+    return p, p.scipy(), O.partition_grid(shape, (2, 2, 1))
+
+
+def _mixed(lu_small, maxit=6, tol=1e-8):
+    p, A, dom = lu_small
+    trace = []
+    r = O.sstep_srecg(A, dom, 4, 2, p.b, tol=tol, maxit=maxit, basis_dtype=np.float32,
+                      inner_tol=1e-5, trace=trace)
+    return r, trace
+
+
+def _a32(lu_small):
+    return lu_small[1].toarray().astype(np.float32).astype(np.float64)
+
+
+def test_clean_binary32_form_passes(lu_small):
+    r, trace = _mixed(lu_small)
+    assert pinlib.binary32_representability_violation(trace) == 0
+    assert pinlib.basis_product_rounding_violation(trace, _a32(lu_small)) <= 0.5 + 1e-6
+    assert pinlib.gram_accuracy_violation(trace) <= 1.0
+
+
+def test_unrounded_cgs_output_is_caught(lu_small, monkeypatch):
+    # CGS2 result left in binary64 instead of stored as a binary32 block
+    def cgs2_no_round(Z, Wp, AWp, dtype=np.float64):
+        if Wp is None or Wp.shape[1] == 0:
+            return Z
+        Z = np.asarray(Z, dtype=np.float64)
+        for _ in range(2):
+            Z = Z - np.asarray(Wp, np.float64) @ (np.asarray(AWp, np.float64).T @ Z)
+        return Z
+
+    monkeypatch.setattr(E, "cgs2_a", cgs2_no_round)
+    r, trace = _mixed(lu_small)
+    assert pinlib.binary32_representability_violation(trace) > 0
+
+
+def test_binary64_matrix_in_basis_product_is_caught(lu_small, monkeypatch):
+    monkeypatch.setattr(E, "basis_matrix", lambda A, dtype: A)
+    r, trace = _mixed(lu_small)
+    assert pinlib.basis_product_rounding_violation(trace, _a32(lu_small)) > 0.5 + 1e-6
+
+
+def test_binary32_matrix_in_residual_replacement_is_caught(lu_small, monkeypatch):
+    p, A, dom = lu_small
+    orig = E.basis_matrix
+    monkeypatch.setattr(E, "true_residual",
+                        lambda A_, b, x: b - orig(A_, np.float32) @ x)
+    r = O.sstep_srecg(A, dom, 4, 2, p.b, tol=1e-11, maxit=500, basis_dtype=np.float32,
+                      inner_tol=1e-5)
+    true = np.linalg.norm(p.b - A @ r.x) / np.linalg.norm(p.b)
+    assert true > 1e-11             # the refinement pin fails
+
+
+def test_binary32_gram_accumulation_is_caught(lu_small, monkeypatch):
+    # A-CholQR with the Gram summed in binary32 (and factorised from that)
+    import scipy.linalg as sla
+
+    def acholqr_gram32(Ab, Z, dtype=np.float64, trace=None):
+        AZ = E._spmm(Ab, Z, dtype)
+        G = (np.asarray(Z, np.float32).T @ np.asarray(AZ, np.float32)).astype(np.float64)
+        G = np.triu(G) + np.triu(G, 1).T
+        if trace is not None:
+            trace.update(Z=Z, AZ=AZ, G=G)
+        R = O.chol_upper(G)
+        W = E._store(sla.solve_triangular(R, E._f64(Z).T, trans="T").T, dtype)
+        AW = E._store(sla.solve_triangular(R, E._f64(AZ).T, trans="T").T, dtype)
+        if trace is not None:
+            trace.update(R=R, W=W, AW=AW)
+        return W, AW, R
+
+    monkeypatch.setattr(E, "a_cholqr", acholqr_gram32)
+    r, trace = _mixed(lu_small, maxit=3)
+    assert pinlib.gram_accuracy_violation(trace) > 1.0
