@@ -91,7 +91,14 @@ typedef struct ecg_opts {
                              the elapsed host time to stderr after every this
                              many s-step iterations and at every restart
                              (default 0: silent) */
-  int32_t reserved[5];    /* must be zero */
+  int32_t permute_domains; /* 1: the solver numbers the rows domain by domain
+                             (the caller's order within a domain) so that
+                             each domain's rows, and the neighbours a sparse
+                             row reaches inside its domain, are contiguous in
+                             device memory; every array argument and result
+                             stays in the caller's order.  0: the caller's
+                             order (default 1) */
+  int32_t reserved[4];    /* must be zero */
 } ecg_opts;
 
 /* Fill *o with the defaults above. */
@@ -158,19 +165,23 @@ int ecg_partition_grid(int64_t nx, int64_t ny, int64_t nz, int32_t px, int32_t p
 
 /*
  * Create a solver for the n x n SPD matrix (rowptr, colind, vals) with the
- * t domains partition[i] in [0, t) and s blocks per iteration.
- * Copies everything to device memory and allocates the workspace: (s+2)
- * pairs of n x t blocks (basis W and its A-image) for ECG_SRECG, one pair
- * per kept block (q_cap_blocks; allocated when first needed) for ECG_SRECG2
- * and ECG_MSDO, plus scratch.
+ * t domains partition[i] in [0, t) and s blocks per iteration.  This is the
+ * set-up of the s-step algorithms (Section 3.1: A symmetric positive
+ * definite; the t domains are the subdomains of the graph of A that the
+ * split operator T of Section 2 uses; Section 4 orders the matrix by them).
+ * Copies everything to device memory (with opts.permute_domains, in the
+ * domain-contiguous row order) and allocates the workspace: (s+2) pairs of
+ * n x t blocks (basis W and its A-image) for ECG_SRECG, one pair per kept
+ * block (q_cap_blocks; allocated when first needed) for ECG_SRECG2 and
+ * ECG_MSDO, plus scratch.
  * Errors: ECG_EINVAL (out == NULL; n <= 0; t < 1; t > 64; t > n; s < 1;
  * rowptr not starting at 0 or decreasing; nnz >= 2^31; a column index out
  * of [0, n); a partition value out of [0, t); an empty domain; a
  * non-finite value; nonzero reserved fields; ECG_SRECG2 or ECG_MSDO with
- * q_cap_blocks in [1, s)), ECG_ENOMEM (the workspace
- * does not fit ws_cap_bytes or device memory), ECG_EDEVICE.  Symmetry and
- * definiteness are not checked here; an indefinite matrix is reported by
- * ecg_solve as ECG_BREAKDOWN.  On error *out is NULL.
+ * q_cap_blocks in [1, s); permute_domains not 0 or 1), ECG_ENOMEM (the
+ * workspace does not fit ws_cap_bytes or device memory), ECG_EDEVICE.
+ * Symmetry and definiteness are not checked here; an indefinite matrix is
+ * reported by ecg_solve as ECG_BREAKDOWN.  On error *out is NULL.
  */
 int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const int32_t* colind,
               const double* vals, const int32_t* partition, int32_t t, int32_t s,
@@ -238,6 +249,15 @@ int ecg_tsplit(ecg_ctx* c, const double* r, double* Z);
  * iteration), ECG_EDEVICE.
  */
 int ecg_get_basis(ecg_ctx* c, double* V, double* AV);
+
+/*
+ * The solver's row order: order[i] (n int32 values, host or device array as
+ * the context's other arrays) is the caller's row that the solver stores as
+ * row i -- the rows of domain 0 in the caller's order, then those of domain
+ * 1, and so on (opts.permute_domains = 1), or i itself (0).
+ * Errors: ECG_EINVAL (NULL argument), ECG_EDEVICE.
+ */
+int ecg_domain_order(ecg_ctx* c, int32_t* order);
 
 /* Per-kernel-class statistics of the last ecg_solve (zeros unless
  * opts.collect_stats = 1). */

@@ -34,7 +34,7 @@ import scipy.sparse as sp
 
 __all__ = [
     "OK", "MAXIT", "BREAKDOWN", "STAGNATED",
-    "csr", "partition_grid", "split_T", "chol_upper", "cgs2_a", "a_cholqr",
+    "csr", "partition_grid", "domain_order", "split_T", "chol_upper", "cgs2_a", "a_cholqr",
     "pre_cholqr", "cg", "srecg", "sstep_srecg", "SolveResult", "basis_matrix", "true_residual",
     "dense_cholesky_solve", "sddmm", "dense_gradient", "Breakdown",
 ]
@@ -77,6 +77,15 @@ def partition_grid(shape, parts) -> np.ndarray:
             dom[row:row + nx] = base + (i * px) // nx
             row += nx
     return dom
+
+
+def domain_order(dom: np.ndarray) -> np.ndarray:
+    """Domain-contiguous row order: the rows of domain 0 in increasing index
+    order, then those of domain 1, and so on (Section 4 reorders the matrix
+    by its Metis domains; READING: rows keep the caller's order within a
+    domain).  order[i] is the original row placed at position i.  Parity:
+    bit-exact (integers)."""
+    return np.argsort(np.asarray(dom), kind="stable").astype(np.int32)
 
 
 def split_T(r: np.ndarray, dom: np.ndarray, t: int) -> np.ndarray:

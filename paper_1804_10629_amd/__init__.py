@@ -51,7 +51,7 @@ class _Opts(ctypes.Structure):
         ("q_cap_blocks", ctypes.c_int32), ("ws_cap_bytes", ctypes.c_int64),
         ("hip_stream", ctypes.c_void_p), ("collect_stats", ctypes.c_int32),
         ("grid", ctypes.c_int32), ("progress_every", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("permute_domains", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -92,6 +92,7 @@ _SIGS = {
     "ecg_tsplit": (ctypes.c_int, [_P, _P, _P]),
     "ecg_get_basis": (ctypes.c_int, [_P, _P, _P]),
     "ecg_last_stats": (ctypes.c_int, [_P, ctypes.POINTER(_Stats)]),
+    "ecg_domain_order": (ctypes.c_int, [_P, _P]),
     "ecg_destroy": (None, [_P]),
 }
 
@@ -205,7 +206,7 @@ class Solver:
                  variant: int = SRECG, orth: int = ACHOLQR, precision: int = FP64,
                  inner_tol: float = 1e-4, max_restarts: int = 20, q_cap_blocks: int = 0,
                  ws_cap_bytes: int = 0, collect_stats: bool = False, grid: int = 0,
-                 progress_every: int = 0):
+                 progress_every: int = 0, permute_domains: bool = True):
         torch = _torch()
         self._ctx = _P()
         o = _Opts()
@@ -215,6 +216,7 @@ class Solver:
         o.inner_tol, o.max_restarts, o.q_cap_blocks = inner_tol, max_restarts, q_cap_blocks
         o.ws_cap_bytes, o.collect_stats, o.grid = ws_cap_bytes, int(collect_stats), grid
         o.progress_every = progress_every
+        o.permute_domains = int(permute_domains)
         o.hip_stream = _stream_ptr()
         self.opts = o
         rp = _dev_tensor(rowptr, torch.int32)
@@ -291,6 +293,13 @@ class Solver:
         AV = torch.empty_like(V)
         _check(lib.ecg_get_basis(self._ctx, V.data_ptr(), AV.data_ptr()))
         return V, AV
+
+    def domain_order(self):
+        """order[i]: the caller's row stored as solver row i (int32 CUDA tensor)."""
+        torch = _torch()
+        out = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        _check(lib.ecg_domain_order(self._ctx, out.data_ptr()))
+        return out
 
     def stats(self) -> dict:
         st = _Stats()

@@ -157,15 +157,20 @@ hipError_t launch_spmm(bool grams, bool has_prev, int tail, const SpArgs<S, SA>&
 template <int TPI, typename S>
 hipError_t launch_xr(const XRArgs<S>& a, int grid, hipStream_t st);
 
+// Optional row maps (nullable): perm[i] is the caller's row of solver row i,
+// emap[p] the caller's entry of solver entry p.
 template <int TPI, typename S>
 hipError_t launch_basis_export(const S* U, const double* rinv, double* V, int64_t n, int t,
-                               int ldv, int col0, hipStream_t st);
+                               int ldv, int col0, const int32_t* perm, hipStream_t st);
 
 hipError_t launch_sddmm(const int32_t* rowptr, const int32_t* colind, const double* lam,
-                        const double* x, double* grad, int64_t n, hipStream_t st);
+                        const double* x, double* grad, int64_t n, const int32_t* perm,
+                        const int32_t* emap, hipStream_t st);
 
-hipError_t launch_pack(const double* X, int k, double* Xp, int TPI, int64_t n, hipStream_t st);
+// pack: row i of Xp = row perm[i] of X; unpack: row i of Xp to row perm[i] of X
+hipError_t launch_pack(const double* X, int k, double* Xp, int TPI, int64_t n,
+                       const int32_t* perm, hipStream_t st);
 hipError_t launch_unpack(const double* Xp, int TPI, double* X, int k, int64_t n,
-                         hipStream_t st);
+                         const int32_t* perm, hipStream_t st);
 
 }  // namespace ecg

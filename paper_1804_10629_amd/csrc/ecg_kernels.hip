@@ -207,6 +207,12 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #ifndef ECG_CS_WPE
 #define ECG_CS_WPE 2
 #endif
+#ifndef ECG_P64
+#define ECG_P64 1              // 64-column product kernel with upper-triangle Grams
+#endif
+#ifndef ECG_P64_MAP
+#define ECG_P64_MAP 0          // its step mapping (p64_steps)
+#endif
 
 
 template <int TPI, typename S = double>
@@ -645,6 +651,11 @@ __device__ void btail_spmm(double* sums, double* tmp, const TailArgs& ta) {
   double* E = sums + 2 * T2;
   double* a = sums + 3 * T2;
   if (tid == 0) s_bad = 0;
+  // F is symmetric: the product kernels may form only its upper triangle
+  for (int idx = tid; idx < T2; idx += blockDim.x) {
+    const int i = idx / TPI, c = idx % TPI;
+    if (i > c) F[idx] = F[c * TPI + i];
+  }
   __syncthreads();
   b_chol<TPI>(G, t, &s_bad);
   b_inverse<TPI>(G, t, tmp);         // G now holds R^{-1}
@@ -2519,6 +2530,267 @@ void k_spmm_cs(SpArgs<S, SA> a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Product kernel for 64-column blocks: A Z, with the Grams G = Z^t (A Z)
+// (A-CholQR), F = (A Z)^t (A Z), E = (A Z_prev)^t (A Z) (the next block's
+// first CGS pass) and a = Z^t r fused in.  At 64 columns the Grams are 27
+// times the arithmetic of the product (three 64 x 64 Grams per row against
+// seven 64-wide FMAs), so the kernel is built around the matrix cores:
+//
+//   * gather: a work-group takes R = 16 rows per step, a wave 4 of them.  A
+//     wave forms one row at a time across its 64 lanes (lane = column), so
+//     the (column, value) pairs of a row are wave-uniform: lanes 8 q + j
+//     load entry j of row q in one instruction, v_readlane hands them to
+//     the scalar unit, and each neighbour row is one coalesced load with a
+//     scalar base.  The rows of Z, A Z and A Z_prev of the step are parked
+//     in LDS tiles (row stride 80 doubles: the four rows of an MFMA operand
+//     fall on alternating halves of the banks).
+//   * Grams: G and F are symmetric, so only their 16 x 16 tiles on or above
+//     the diagonal are formed (10 of 16 each; the tail mirrors F), E in
+//     full: 36 tiles of MFMA f64 16x16x4 (K = the step's rows), 9 per wave,
+//     assigned so that every wave has the same count (20 tiles, 5 per wave,
+//     without E).  Tiles of a wave are compile-time (one instantiation of
+//     the loop per wave).
+//   * two LDS buffers: the next step's gather fills one while slower waves
+//     still read the other, so one barrier per step suffices.
+// ---------------------------------------------------------------------------
+
+constexpr int kP64R = 16;      // rows per work-group step
+constexpr int kP64LD = 80;     // LDS tile row stride (doubles)
+#ifndef ECG_P64_CH
+#define ECG_P64_CH 7
+#endif
+constexpr int kP64CH = ECG_P64_CH;   // entries of a row gathered per chunk (<= 8)
+
+// tile code: mat * 16 + a * 4 + b, tile (a, b) of mat 0 = G, 1 = F, 2 = E:
+// the 16 x 16 block rows 16 a.., columns 16 b..
+constexpr int kP64TileE[4][9] = {
+    {0x03, 0x07, 0x0B, 0x0F, 0x13, 0x17, 0x1B, 0x1F, 0x23},
+    {0x27, 0x2B, 0x2F, 0x02, 0x06, 0x0A, 0x12, 0x16, 0x1A},
+    {0x22, 0x26, 0x2A, 0x2E, 0x01, 0x05, 0x11, 0x15, 0x21},
+    {0x25, 0x29, 0x2D, 0x00, 0x10, 0x20, 0x24, 0x28, 0x2C}};
+constexpr int kP64TileN[4][5] = {{0x03, 0x07, 0x0B, 0x0F, 0x13},
+                                            {0x17, 0x1B, 0x1F, 0x02, 0x06},
+                                            {0x0A, 0x12, 0x16, 0x1A, 0x01},
+                                            {0x05, 0x11, 0x15, 0x00, 0x10}};
+
+constexpr int p64_tile(int w, bool hp, int k) { return hp ? kP64TileE[w][k] : kP64TileN[w][k]; }
+
+// Row steps of the 64-column product.  ECG_P64_MAP 0: each XCD sweeps a
+// contiguous eighth of the rows (my_steps); 1: all work-groups sweep the rows
+// together, the work-groups of one XCD taking adjacent steps, so that the
+// +-nx*ny neighbour planes of every XCD are the same few planes (shared in
+// the last-level cache) instead of eight separate ones.
+__device__ __forceinline__ Steps p64_steps(int64_t nsteps) {
+  const int G = gridDim.x;
+  if (ECG_P64_MAP == 1 && G % 8 == 0 && G >= 64) {
+    const int xcd = blockIdx.x % 8, local = blockIdx.x / 8, per = G / 8;
+    return Steps{(int64_t)xcd * per + local, nsteps, G};
+  }
+  return my_steps(nsteps);
+}
+
+template <typename S, typename SA, bool GRAMS, bool HAS_PREV, int W>
+__device__ __forceinline__ void p64_run(const SpArgs<S, SA>& a, double* tiles, double* asum) {
+  constexpr int TPI = 64, T2 = TPI * TPI, R = kP64R, LD = kP64LD, CH = kP64CH;
+  constexpr int NT = HAS_PREV ? 9 : 5;
+  constexpr int TB = 3 * R * LD;      // doubles per buffer: Z, A Z, A Z_prev tiles
+  const int lane = threadIdx.x & 63;
+  const int m = lane & 15, rq = lane >> 4;
+  const int64_t n = a.n;
+  const int nnz_last = a.rowptr[n] - 1;
+  const Steps sp = p64_steps((n + R - 1) / R);
+  // lanes 8 q + j (q < 4, j < CH) hold entry j of the current chunk of row q
+  const int q_l = (lane >> 3) & 3, j_l = lane & 7;
+
+  // software pipeline: row pointers three steps ahead, the (column, value)
+  // pairs of a row's first chunk two steps ahead, the gathered neighbour
+  // rows and the own rows one step ahead (issued before the current step's
+  // matrix-core phase)
+  struct RowPtr { int p0, p1; };
+  struct Head { int col; double val; };
+  struct Rows { double zg[4][CH]; double zo[4], po[4], rv[4]; };
+  auto load_rowptr = [&](int64_t st, RowPtr& rp) {
+    const int64_t rl = st * R + 4 * W + q_l;
+    const int64_t rlc = rl < n ? rl : n - 1;
+    rp.p0 = ld_s(a.rowptr + rlc);
+    rp.p1 = ld_s(a.rowptr + rlc + 1);
+  };
+  auto load_head = [&](const RowPtr& rp, int c, Head& h) {
+    // entries past the row's end (or past CH) read a valid entry with the
+    // value zero
+    const int idx = rp.p0 + c + j_l;
+    const int idc = min(idx, nnz_last);
+    h.col = ld_s(a.colind + idc);
+    h.val = static_cast<double>(ld_s(a.vals + idc)) *
+            opaque(idx < rp.p1 && j_l < CH ? 1.0 : 0.0);
+  };
+  auto load_rows = [&](int64_t st, const Head& h, Rows& d) {
+    static_for<4>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      static_for<CH>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        const int cj = __builtin_amdgcn_readlane(h.col, 8 * q + j);
+        d.zg[q][j] = ld(a.Z + (int64_t)cj * TPI + lane);
+      });
+    });
+    if constexpr (GRAMS) {
+      for (int q = 0; q < 4; ++q) {
+        const int64_t row = st * R + 4 * W + q;
+        const int64_t rc = row < n ? row : n - 1;
+        d.zo[q] = ld(a.Z + rc * TPI + lane);
+        d.po[q] = HAS_PREV ? static_cast<double>(ld_s(a.AZprev + rc * TPI + lane)) : 0.0;
+        d.rv[q] = ld_s(a.rvec + rc);
+      }
+    }
+  };
+  auto head_val = [&](const Head& h, int q, int j) {
+    const uint64_t vb = __builtin_bit_cast(uint64_t, h.val);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)vb, 8 * q + j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(vb >> 32), 8 * q + j);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+  };
+
+  d4 acc[NT];
+  for (int k = 0; k < NT; ++k) acc[k] = d4{0.0, 0.0, 0.0, 0.0};
+  double av = 0.0;
+  int buf = 0;
+
+  RowPtr rp_cur{0, 0}, rp1{0, 0}, rp2{0, 0};
+  Head h_cur{0, 0.0}, h1{0, 0.0};
+  Rows d_cur;
+  int64_t step = sp.first;
+  const int64_t st = sp.stride;
+  if (step < sp.end) {
+    load_rowptr(step, rp_cur);
+    if (step + st < sp.end) load_rowptr(step + st, rp1);
+    if (step + 2 * st < sp.end) load_rowptr(step + 2 * st, rp2);
+    load_head(rp_cur, 0, h_cur);
+    if (step + st < sp.end) load_head(rp1, 0, h1);
+    load_rows(step, h_cur, d_cur);
+  }
+  for (; step < sp.end; step += st) {
+    const bool has1 = step + st < sp.end, has2 = step + 2 * st < sp.end,
+               has3 = step + 3 * st < sp.end;
+    const int64_t row0 = step * R + 4 * W;
+    double y[4];
+    static_for<4>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      double acc_y = 0.0;
+      static_for<CH>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        acc_y = __builtin_fma(head_val(h_cur, q, j), d_cur.zg[q][j], acc_y);
+      });
+      y[q] = acc_y;
+    });
+    // rows longer than one chunk (none in 5- and 7-point stencils)
+    int maxlen = 0;
+    for (int q = 0; q < 4; ++q)
+      maxlen = max(maxlen, __builtin_amdgcn_readlane(rp_cur.p1 - rp_cur.p0, 8 * q));
+    for (int c = CH; c < maxlen; c += CH) {
+      Head h;
+      load_head(rp_cur, c, h);
+      static_for<4>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        static_for<CH>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          const int cj = __builtin_amdgcn_readlane(h.col, 8 * q + j);
+          y[q] = __builtin_fma(head_val(h, q, j), ld(a.Z + (int64_t)cj * TPI + lane), y[q]);
+        });
+      });
+    }
+    for (int q = 0; q < 4; ++q)
+      if (row0 + q < n) st_s(a.AZ + (row0 + q) * TPI + lane, static_cast<S>(y[q]));
+    if constexpr (GRAMS) {
+      double* tb = tiles + buf * TB;
+      for (int q = 0; q < 4; ++q) {
+        const int r = 4 * W + q;
+        const double okf = row0 + q < n ? 1.0 : 0.0;
+        // the stored (rounded) value of A Z enters the Grams
+        tb[r * LD + lane] = d_cur.zo[q] * okf;
+        tb[R * LD + r * LD + lane] = static_cast<double>(static_cast<S>(y[q])) * okf;
+        if constexpr (HAS_PREV) tb[2 * R * LD + r * LD + lane] = d_cur.po[q] * okf;
+        av = __builtin_fma(d_cur.zo[q] * okf, d_cur.rv[q], av);
+      }
+      __syncthreads();
+    }
+    // the next steps' loads go out before this step's matrix-core phase
+    Rows d_nxt;
+    Head h2{0, 0.0};
+    RowPtr rp3{0, 0};
+    if (has1) load_rows(step + st, h1, d_nxt);
+    if (has2) load_head(rp2, 0, h2);
+    if (has3) load_rowptr(step + 3 * st, rp3);
+    if constexpr (GRAMS) {
+      const double* X = tiles + buf * TB;
+      const double* Y = X + R * LD;
+      const double* P = X + 2 * R * LD;
+      for (int kk = 0; kk < R / 4; ++kk) {
+        const int ro = (4 * kk + rq) * LD + m;
+        static_for<NT>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          constexpr int code = p64_tile(W, HAS_PREV, k);
+          constexpr int mat = code >> 4, ta = (code >> 2) & 3, tbk = code & 3;
+          const double* M = mat == 0 ? X : (mat == 1 ? Y : P);
+          acc[k] = mfma16(M[ro + 16 * ta], Y[ro + 16 * tbk], acc[k]);
+        });
+      }
+      buf ^= 1;
+    }
+    d_cur = d_nxt;
+    h_cur = h1;
+    h1 = h2;
+    rp_cur = rp1;
+    rp1 = rp2;
+    rp2 = rp3;
+  }
+  if constexpr (GRAMS) {
+    constexpr int L = 3 * T2 + TPI;
+    double* mine = a.rc.partials + (size_t)blockIdx.x * L;
+    static_for<NT>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      constexpr int code = p64_tile(W, HAS_PREV, k);
+      constexpr int mat = code >> 4, ta = (code >> 2) & 3, tbk = code & 3;
+      for (int v = 0; v < 4; ++v)
+        mine[mat * T2 + (16 * ta + 4 * v + rq) * TPI + 16 * tbk + m] = acc[k][v];
+    });
+    asum[W * 64 + lane] = av;
+  }
+}
+
+template <typename S, typename SA, bool GRAMS, bool HAS_PREV>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_spmm64(SpArgs<S, SA> a) {
+  constexpr int T2 = 64 * 64;
+  __shared__ double tiles[GRAMS ? 2 * 3 * kP64R * kP64LD : 1];
+  __shared__ double asum[GRAMS ? 4 * 64 : 1];
+  const int wave = threadIdx.x >> 6;
+  switch (wave) {
+    case 0: p64_run<S, SA, GRAMS, HAS_PREV, 0>(a, tiles, asum); break;
+    case 1: p64_run<S, SA, GRAMS, HAS_PREV, 1>(a, tiles, asum); break;
+    case 2: p64_run<S, SA, GRAMS, HAS_PREV, 2>(a, tiles, asum); break;
+    default: p64_run<S, SA, GRAMS, HAS_PREV, 3>(a, tiles, asum); break;
+  }
+  if constexpr (GRAMS) {
+    constexpr int L = 3 * T2 + 64;
+    double* mine = a.rc.partials + (size_t)blockIdx.x * L;
+    // tiles below the diagonal of G and F are not formed: zero (the tail
+    // mirrors F and reads only the upper triangle of G); E without a
+    // previous block is zero
+    for (int idx = threadIdx.x; idx < 3 * T2; idx += blockDim.x) {
+      const int mat = idx / T2, e = idx % T2;
+      const int br = (e / 64) / 16, bc = (e % 64) / 16;
+      if ((mat < 2 && br > bc) || (mat == 2 && !HAS_PREV)) mine[idx] = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      double s = 0.0;
+      for (int w = 0; w < 4; ++w) s += asum[w * 64 + threadIdx.x];
+      mine[3 * T2 + threadIdx.x] = s;
+    }
+  }
+}
+
 // x += sum_i U_i beta_i ; r -= sum_i AU_i beta_i ; ||r||^2.  Blocks are
 // taken four at a time so that eight loads per row are in flight.
 template <int TPI, typename S, int NB4>
@@ -2662,7 +2934,8 @@ __global__ ECG_STREAM void k_xr_wide(XRArgs<S> a) {
 
 template <int TPI, typename S>
 __global__ void k_basis_export(const S* __restrict__ U, const double* __restrict__ rinv,
-                               double* __restrict__ V, int64_t n, int t, int ldv, int col0) {
+                               double* __restrict__ V, int64_t n, int t, int ldv, int col0,
+                               const int32_t* __restrict__ perm) {
   const int64_t total = n * t;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -2670,44 +2943,57 @@ __global__ void k_basis_export(const S* __restrict__ U, const double* __restrict
     const int c = (int)(idx % t);
     double acc = 0.0;
     for (int k = 0; k <= c; ++k) acc += ld(U + row * TPI + k) * rinv[k * TPI + c];
-    V[row * ldv + col0 + c] = acc;
+    const int64_t orow = perm ? perm[row] : row;
+    V[orow * ldv + col0 + c] = acc;
   }
 }
 
+// grad[p] = -lam[row(p)] x[col(p)] for every stored entry p of the caller's
+// matrix.  The kernel walks the solver's (possibly domain-permuted) rows;
+// with a permutation, perm maps solver rows to caller rows and emap solver
+// entries to caller entries (lam, x and grad are in the caller's order).
 __global__ void k_sddmm(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
                         const double* __restrict__ lam, const double* __restrict__ x,
-                        double* __restrict__ grad, int64_t n) {
+                        double* __restrict__ grad, int64_t n, const int32_t* __restrict__ perm,
+                        const int32_t* __restrict__ emap) {
   for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
        row += (int64_t)gridDim.x * blockDim.x) {
-    const double l = lam[row];
-    for (int p = rowptr[row]; p < rowptr[row + 1]; ++p) grad[p] = -l * x[colind[p]];
+    const double l = lam[perm ? perm[row] : row];
+    for (int p = rowptr[row]; p < rowptr[row + 1]; ++p) {
+      const int c = colind[p];
+      grad[emap ? emap[p] : p] = -l * x[perm ? perm[c] : c];
+    }
   }
 }
 
+// Row-major n x k block X to the n x TPI block Xp (padding columns zero);
+// with perm, row i of Xp is row perm[i] of X.
 __global__ void k_pack(const double* __restrict__ X, int k, double* __restrict__ Xp, int TPI,
-                       int64_t n) {
+                       int64_t n, const int32_t* __restrict__ perm) {
   const int64_t total = n * TPI;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t row = idx / TPI;
     const int c = (int)(idx % TPI);
-    Xp[idx] = c < k ? X[row * k + c] : 0.0;
+    const int64_t src = perm ? perm[row] : row;
+    Xp[idx] = c < k ? X[src * k + c] : 0.0;
   }
 }
 
+// The first k columns of the n x TPI block Xp to the n x k block X; with
+// perm, row i of Xp goes to row perm[i] of X.
 __global__ void k_unpack(const double* __restrict__ Xp, int TPI, double* __restrict__ X, int k,
-                         int64_t n) {
+                         int64_t n, const int32_t* __restrict__ perm) {
   const int64_t total = n * k;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t row = idx / k;
     const int c = (int)(idx % k);
-    X[idx] = Xp[row * TPI + c];
+    const int64_t dst = perm ? perm[row] : row;
+    X[dst * k + c] = Xp[row * TPI + c];
   }
 }
 
-// Group sums: work-group (g, chunk) adds, for 256 consecutive entries, the
-// partials of producer work-groups g*GS .. g*GS + GS - 1 in index order.
 __global__ __launch_bounds__(kThreads) void k_reduce_groups(const double* __restrict__ partials,
                                                             int G, int L, int GS,
                                                             double* __restrict__ groups) {
@@ -2913,6 +3199,18 @@ hipError_t launch_update_gram(int nu, int ng, bool ident0, bool write_out, int t
 template <int TPI, typename S, typename SA>
 hipError_t launch_spmm(bool grams, bool has_prev, int tail, const SpArgs<S, SA>& a, int grid,
                        hipStream_t st) {
+  if constexpr (uses_cs(TPI) && ECG_P64) {
+    // kCSGroups work-groups (one Gram partial each) per unit of `grid`
+    const dim3 blk(kThreads), g(grid * kCSGroups);
+    if (grams && tail != TAIL_SPMM) return hipErrorInvalidValue;
+    if (!grams)
+      hipLaunchKernelGGL((k_spmm64<S, SA, false, false>), g, blk, 0, st, a);
+    else if (has_prev)
+      hipLaunchKernelGGL((k_spmm64<S, SA, true, true>), g, blk, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_spmm64<S, SA, true, false>), g, blk, 0, st, a);
+    return hipGetLastError();
+  }
   if constexpr (uses_cs(TPI)) {
     // kCSGroups row groups (one Gram partial each) per unit of `grid`
     const dim3 blk(cs_threads(TPI)), g(grid * (kCSGroups / CsCfg<TPI>::RGRP));
@@ -3017,28 +3315,31 @@ hipError_t launch_xr(const XRArgs<S>& a, int grid, hipStream_t st) {
 
 template <int TPI, typename S>
 hipError_t launch_basis_export(const S* U, const double* rinv, double* V, int64_t n, int t,
-                               int ldv, int col0, hipStream_t st) {
+                               int ldv, int col0, const int32_t* perm, hipStream_t st) {
   hipLaunchKernelGGL((k_basis_export<TPI, S>), dim3(simple_grid(n * t)), dim3(kThreads), 0, st,
-                     U, rinv, V, n, t, ldv, col0);
+                     U, rinv, V, n, t, ldv, col0, perm);
   return hipGetLastError();
 }
 
 hipError_t launch_sddmm(const int32_t* rowptr, const int32_t* colind, const double* lam,
-                        const double* x, double* grad, int64_t n, hipStream_t st) {
+                        const double* x, double* grad, int64_t n, const int32_t* perm,
+                        const int32_t* emap, hipStream_t st) {
   hipLaunchKernelGGL(k_sddmm, dim3(simple_grid(n)), dim3(kThreads), 0, st, rowptr, colind, lam, x,
-                     grad, n);
+                     grad, n, perm, emap);
   return hipGetLastError();
 }
 
-hipError_t launch_pack(const double* X, int k, double* Xp, int TPI, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_pack, dim3(simple_grid(n * TPI)), dim3(kThreads), 0, st, X, k, Xp, TPI, n);
+hipError_t launch_pack(const double* X, int k, double* Xp, int TPI, int64_t n,
+                       const int32_t* perm, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack, dim3(simple_grid(n * TPI)), dim3(kThreads), 0, st, X, k, Xp, TPI, n,
+                     perm);
   return hipGetLastError();
 }
 
 hipError_t launch_unpack(const double* Xp, int TPI, double* X, int k, int64_t n,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_unpack, dim3(simple_grid(n * k)), dim3(kThreads), 0, st, Xp, TPI, X, k,
-                     n);
+                         const int32_t* perm, hipStream_t st) {
+  hipLaunchKernelGGL(k_unpack, dim3(simple_grid(n * k)), dim3(kThreads), 0, st, Xp, TPI, X, k, n,
+                     perm);
   return hipGetLastError();
 }
 
@@ -3049,7 +3350,7 @@ hipError_t launch_unpack(const double* Xp, int TPI, double* X, int k, int64_t n,
                                                  int, hipStream_t);                        \
   template hipError_t launch_xr<TPI, S>(const XRArgs<S>&, int, hipStream_t);               \
   template hipError_t launch_basis_export<TPI, S>(const S*, const double*, double*, int64_t, \
-                                                  int, int, int, hipStream_t);
+                                                  int, int, int, const int32_t*, hipStream_t);
 ECG_INST(16, double)
 ECG_INST(32, double)
 ECG_INST(64, double)

@@ -72,6 +72,11 @@ struct ecg_ctx {
   int32_t* rowptr = nullptr;
   int32_t* colind = nullptr;
   int32_t* dom = nullptr;
+  // domain-contiguous row order (opts.permute_domains): perm[i] is the
+  // caller's row of solver row i, emap[p] the caller's entry of solver
+  // entry p; both NULL when the caller's order is kept
+  int32_t* perm = nullptr;
+  int32_t* emap = nullptr;
   double* vals = nullptr;
   float* vals32 = nullptr;
   double* b = nullptr;
@@ -174,6 +179,8 @@ void ecg_opts_default(ecg_opts* o) {
   o->hip_stream = nullptr;
   o->collect_stats = 0;
   o->grid = 0;
+  o->progress_every = 0;
+  o->permute_domains = 1;
 }
 
 const char* ecg_version(void) { return "ecg-mi355x 0.1.0 (gfx950)"; }
@@ -257,6 +264,7 @@ extern "C" void ecg_destroy(ecg_ctx* c) {
     if (p) (void)hipFree(p);
   };
   f(c->rowptr); f(c->colind); f(c->dom); f(c->vals); f(c->vals32);
+  f(c->perm); f(c->emap);
   f(c->b); f(c->x); f(c->r); f(c->x2); f(c->r2);
   for (void* p : c->U) f(p);
   for (void* p : c->AU) f(p);
@@ -321,7 +329,7 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   ecg_opts o;
   if (opts) o = *opts;
   else ecg_opts_default(&o);
-  for (int i = 0; i < 5; ++i)
+  for (int i = 0; i < 4; ++i)
     if (o.reserved[i] != 0) return fail(ECG_EINVAL, "reserved option fields must be zero");
   if (!rowptr || !colind || !vals || !partition) return fail(ECG_EINVAL, "NULL array argument");
   if (n <= 0) return fail(ECG_EINVAL, "n must be positive");
@@ -334,6 +342,8 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   if (o.orth != ECG_ACHOLQR && o.orth != ECG_PRECHOLQR) return fail(ECG_EINVAL, "bad orth");
   if (o.precision != ECG_FP64 && o.precision != ECG_MIXED) return fail(ECG_EINVAL, "bad precision");
   if (o.device_ptrs != 0 && o.device_ptrs != 1) return fail(ECG_EINVAL, "bad device_ptrs");
+  if (o.permute_domains != 0 && o.permute_domains != 1)
+    return fail(ECG_EINVAL, "bad permute_domains");
   if (!(o.inner_tol >= 0.0 && o.inner_tol < 1.0)) return fail(ECG_EINVAL, "inner_tol must be in [0, 1)");
   if (o.max_restarts < 0 || o.q_cap_blocks < 0 || o.ws_cap_bytes < 0 || o.grid < 0 ||
       o.progress_every < 0)
@@ -375,6 +385,44 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   }
   for (int d = 0; d < t; ++d)
     if (dsize[d] == 0) return fail(ECG_EINVAL, "empty domain " + std::to_string(d));
+
+  // Domain-contiguous order (the paper reorders the matrix by its Metis
+  // domains, Section 4): solver row i is the caller's row perm[i], rows
+  // sorted by domain, keeping the caller's order within a domain; column
+  // indices renumbered and sorted ascending within each row.
+  const bool permute = o.permute_domains == 1;
+  std::vector<int32_t> perm_h, emap_h, prp_h, pci_h, pdom_h;
+  std::vector<double> pv_h;
+  if (permute) {
+    std::vector<int64_t> pos(t + 1, 0);
+    for (int d = 0; d < t; ++d) pos[d + 1] = pos[d] + dsize[d];
+    perm_h.resize(n);
+    std::vector<int32_t> iperm(n);
+    for (int64_t i = 0; i < n; ++i) perm_h[pos[pd[i]]++] = (int32_t)i;
+    for (int64_t j = 0; j < n; ++j) iperm[perm_h[j]] = (int32_t)j;
+    prp_h.resize(n + 1);
+    pci_h.resize(nnz);
+    pv_h.resize(nnz);
+    emap_h.resize(nnz);
+    pdom_h.resize(n);
+    std::vector<std::pair<int32_t, int32_t>> ent;
+    int64_t k = 0;
+    prp_h[0] = 0;
+    for (int64_t j = 0; j < n; ++j) {
+      const int32_t p = perm_h[j];
+      ent.clear();
+      for (int32_t e = rp[p]; e < rp[p + 1]; ++e) ent.emplace_back(iperm[ci[e]], e);
+      std::sort(ent.begin(), ent.end());
+      for (const auto& ce : ent) {
+        pci_h[k] = ce.first;
+        pv_h[k] = vv[ce.second];
+        emap_h[k] = ce.second;
+        ++k;
+      }
+      prp_h[j + 1] = (int32_t)k;
+      pdom_h[j] = pd[p];
+    }
+  }
 
   rc = check_device();
   if (rc) return rc;
@@ -453,6 +501,10 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   ALLOC(c->x2, double, n);
   ALLOC(c->r2, double, n);
   if (o.precision == ECG_MIXED) ALLOC(c->vals32, float, nnz);
+  if (permute) {
+    ALLOC(c->perm, int32_t, n);
+    ALLOC(c->emap, int32_t, nnz);
+  }
   // SRE-CG2 keeps one block pair per block since the last restart; its
   // pairs are allocated when a solve first needs them (grow_slots)
   c->U.assign(c->nslot, nullptr);
@@ -484,13 +536,27 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
     HIP_TRY(hipMemcpyAsync(dst, src, bytes, kind, c->st));
     return ECG_OK;
   };
-  if ((rc = up(c->rowptr, rowptr, sizeof(int32_t) * (n + 1)))) return cleanup(rc);
-  if ((rc = up(c->colind, colind, sizeof(int32_t) * nnz))) return cleanup(rc);
-  if ((rc = up(c->vals, vals, sizeof(double) * nnz))) return cleanup(rc);
-  if ((rc = up(c->dom, partition, sizeof(int32_t) * n))) return cleanup(rc);
+  auto uph = [&](void* dst, const void* src, size_t bytes) -> int {
+    HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return ECG_OK;
+  };
+  if (permute) {
+    if ((rc = uph(c->rowptr, prp_h.data(), sizeof(int32_t) * (n + 1)))) return cleanup(rc);
+    if ((rc = uph(c->colind, pci_h.data(), sizeof(int32_t) * nnz))) return cleanup(rc);
+    if ((rc = uph(c->vals, pv_h.data(), sizeof(double) * nnz))) return cleanup(rc);
+    if ((rc = uph(c->dom, pdom_h.data(), sizeof(int32_t) * n))) return cleanup(rc);
+    if ((rc = uph(c->perm, perm_h.data(), sizeof(int32_t) * n))) return cleanup(rc);
+    if ((rc = uph(c->emap, emap_h.data(), sizeof(int32_t) * nnz))) return cleanup(rc);
+  } else {
+    if ((rc = up(c->rowptr, rowptr, sizeof(int32_t) * (n + 1)))) return cleanup(rc);
+    if ((rc = up(c->colind, colind, sizeof(int32_t) * nnz))) return cleanup(rc);
+    if ((rc = up(c->vals, vals, sizeof(double) * nnz))) return cleanup(rc);
+    if ((rc = up(c->dom, partition, sizeof(int32_t) * n))) return cleanup(rc);
+  }
   if (o.precision == ECG_MIXED) {
+    const double* vsrc = permute ? pv_h.data() : vv;
     std::vector<float> v32((size_t)nnz);
-    for (int64_t p = 0; p < nnz; ++p) v32[p] = (float)vv[p];
+    for (int64_t p = 0; p < nnz; ++p) v32[p] = (float)vsrc[p];
     if (hipMemcpy(c->vals32, v32.data(), sizeof(float) * nnz, hipMemcpyHostToDevice) != hipSuccess)
       return cleanup(fail(ECG_EDEVICE, "upload of binary32 values failed"));
   }
@@ -1037,8 +1103,22 @@ int solve_impl(ecg_ctx* c, const double* b, double* x, double tol, int32_t maxit
   const bool dev = c->o.device_ptrs == 1;
   const hipMemcpyKind in = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   const hipMemcpyKind outk = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  HIP_TRY(hipMemcpyAsync(c->b, b, sizeof(double) * c->n, in, c->st));
-  HIP_TRY(hipMemcpyAsync(c->x, x, sizeof(double) * c->n, in, c->st));
+  if (c->perm) {
+    // into the solver's row order (host arrays through the spare vectors)
+    const double* bs = b;
+    const double* xs = x;
+    if (!dev) {
+      HIP_TRY(hipMemcpyAsync(c->x2, b, sizeof(double) * c->n, in, c->st));
+      HIP_TRY(hipMemcpyAsync(c->r2, x, sizeof(double) * c->n, in, c->st));
+      bs = c->x2;
+      xs = c->r2;
+    }
+    HIP_TRY(launch_pack(bs, 1, c->b, 1, c->n, c->perm, c->st));
+    HIP_TRY(launch_pack(xs, 1, c->x, 1, c->n, c->perm, c->st));
+  } else {
+    HIP_TRY(hipMemcpyAsync(c->b, b, sizeof(double) * c->n, in, c->st));
+    HIP_TRY(hipMemcpyAsync(c->x, x, sizeof(double) * c->n, in, c->st));
+  }
   HIP_TRY(hipEventRecord(c->ev_solve0, c->st));
   int st;
   switch (c->tpi) {
@@ -1054,7 +1134,17 @@ int solve_impl(ecg_ctx* c, const double* b, double* x, double tol, int32_t maxit
     return st;
   }
   HIP_TRY(hipEventRecord(c->ev_solve1, c->st));
-  HIP_TRY(hipMemcpyAsync(x, c->x, sizeof(double) * c->n, outk, c->st));
+  if (c->perm) {
+    // back to the caller's row order (x2 is free after the solve)
+    if (dev) {
+      HIP_TRY(launch_unpack(c->x, 1, x, 1, c->n, c->perm, c->st));
+    } else {
+      HIP_TRY(launch_unpack(c->x, 1, c->x2, 1, c->n, c->perm, c->st));
+      HIP_TRY(hipMemcpyAsync(x, c->x2, sizeof(double) * c->n, outk, c->st));
+    }
+  } else {
+    HIP_TRY(hipMemcpyAsync(x, c->x, sizeof(double) * c->n, outk, c->st));
+  }
   HIP_TRY(hipStreamSynchronize(c->st));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, c->ev_solve0, c->ev_solve1));
@@ -1111,7 +1201,7 @@ extern "C" int ecg_sddmm(ecg_ctx* c, const double* lambda, const double* x, doub
     dx = tx;
     dg = tg;
   }
-  hipError_t e = launch_sddmm(c->rowptr, c->colind, dl, dx, dg, c->n, c->st);
+  hipError_t e = launch_sddmm(c->rowptr, c->colind, dl, dx, dg, c->n, c->perm, c->emap, c->st);
   if (e == hipSuccess && !dev)
     e = hipMemcpyAsync(grad_vals, tg, sizeof(double) * c->nnz, hipMemcpyDeviceToHost, c->st);
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
@@ -1163,7 +1253,7 @@ extern "C" int ecg_spmm(ecg_ctx* c, const double* X, double* Y, int32_t k) {
   if (dev) Xin = (double*)X;
   else HIP_TRY(hipMemcpyAsync(Xin, X, sizeof(double) * c->n * k, hipMemcpyHostToDevice, c->st));
   // pack to n x tpi in scratch, product into scratch2 (after the pack consumed it)
-  HIP_TRY(launch_pack(Xin, k, c->scratch, tpi, c->n, c->st));
+  HIP_TRY(launch_pack(Xin, k, c->scratch, tpi, c->n, c->perm, c->st));
   switch (tpi) {
     case 16: rc = spmm_op<16>(c, c->scratch, c->scratch2); break;
     case 32: rc = spmm_op<32>(c, c->scratch, c->scratch2); break;
@@ -1171,9 +1261,9 @@ extern "C" int ecg_spmm(ecg_ctx* c, const double* X, double* Y, int32_t k) {
   }
   if (rc) return rc;
   if (dev) {
-    HIP_TRY(launch_unpack(c->scratch2, tpi, Y, k, c->n, c->st));
+    HIP_TRY(launch_unpack(c->scratch2, tpi, Y, k, c->n, c->perm, c->st));
   } else {
-    HIP_TRY(launch_unpack(c->scratch2, tpi, c->scratch, k, c->n, c->st));
+    HIP_TRY(launch_unpack(c->scratch2, tpi, c->scratch, k, c->n, c->perm, c->st));
     HIP_TRY(hipMemcpyAsync(Y, c->scratch, sizeof(double) * c->n * k, hipMemcpyDeviceToHost, c->st));
   }
   HIP_TRY(hipStreamSynchronize(c->st));
@@ -1188,6 +1278,10 @@ extern "C" int ecg_tsplit(ecg_ctx* c, const double* r, double* Z) {
   double* rin = c->scratch2;
   if (dev) rin = (double*)r;
   else HIP_TRY(hipMemcpyAsync(rin, r, sizeof(double) * c->n, hipMemcpyHostToDevice, c->st));
+  if (c->perm) {   // r in the solver's row order (x2 is free between solves)
+    HIP_TRY(launch_pack(rin, 1, c->x2, 1, c->n, c->perm, c->st));
+    rin = c->x2;
+  }
   double* out = c->scratch;
   switch (c->tpi) {
     case 16: HIP_TRY((launch_tsplit<16, double>(rin, c->dom, out, c->n, 0, c->st))); break;
@@ -1195,7 +1289,7 @@ extern "C" int ecg_tsplit(ecg_ctx* c, const double* r, double* Z) {
     default: HIP_TRY((launch_tsplit<64, double>(rin, c->dom, out, c->n, 0, c->st))); break;
   }
   double* dst = dev ? Z : c->scratch2;
-  HIP_TRY(launch_unpack(out, c->tpi, dst, c->t, c->n, c->st));
+  HIP_TRY(launch_unpack(out, c->tpi, dst, c->t, c->n, c->perm, c->st));
   if (!dev)
     HIP_TRY(hipMemcpyAsync(Z, dst, sizeof(double) * c->n * c->t, hipMemcpyDeviceToHost, c->st));
   HIP_TRY(hipStreamSynchronize(c->st));
@@ -1227,16 +1321,16 @@ extern "C" int ecg_get_basis(ecg_ctx* c, double* V, double* AV) {
 #define EXP(TPI)                                                                                \
   if (mixed) {                                                                                  \
     e = launch_basis_export<TPI, float>((const float*)c->U[slot], ri, dv, c->n, c->t, st,       \
-                                        i * c->t, c->st);                                       \
+                                        i * c->t, c->perm, c->st);                                       \
     if (e == hipSuccess)                                                                        \
       e = launch_basis_export<TPI, float>((const float*)c->AU[slot], ri, dav, c->n, c->t, st,   \
-                                          i * c->t, c->st);                                     \
+                                          i * c->t, c->perm, c->st);                                     \
   } else {                                                                                      \
     e = launch_basis_export<TPI, double>((const double*)c->U[slot], ri, dv, c->n, c->t, st,     \
-                                         i * c->t, c->st);                                      \
+                                         i * c->t, c->perm, c->st);                                      \
     if (e == hipSuccess)                                                                        \
       e = launch_basis_export<TPI, double>((const double*)c->AU[slot], ri, dav, c->n, c->t, st, \
-                                           i * c->t, c->st);                                    \
+                                           i * c->t, c->perm, c->st);                                    \
   }
     if (c->tpi == 16) { EXP(16) }
     else if (c->tpi == 32) { EXP(32) }
@@ -1254,6 +1348,23 @@ extern "C" int ecg_get_basis(ecg_ctx* c, double* V, double* AV) {
     (void)hipFree(dav);
   }
   if (e != hipSuccess) return fail(ECG_EDEVICE, std::string("get_basis: ") + hipGetErrorString(e));
+  return ECG_OK;
+}
+
+extern "C" int ecg_domain_order(ecg_ctx* c, int32_t* order) {
+  if (!c || !order) return fail(ECG_EINVAL, "NULL argument");
+  const bool dev = c->o.device_ptrs == 1;
+  std::vector<int32_t> h;
+  if (!c->perm) {
+    h.resize(c->n);
+    for (int64_t i = 0; i < c->n; ++i) h[i] = (int32_t)i;
+    HIP_TRY(hipMemcpy(order, h.data(), sizeof(int32_t) * c->n,
+                      dev ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+    return ECG_OK;
+  }
+  HIP_TRY(hipMemcpyAsync(order, c->perm, sizeof(int32_t) * c->n,
+                         dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
   return ECG_OK;
 }
 

@@ -45,7 +45,8 @@ def test_opts_default():
     E.lib.ecg_opts_default(ctypes.byref(o))
     assert (o.variant, o.orth, o.precision, o.device_ptrs) == (0, 0, 0, 0)
     assert o.inner_tol == 1e-4 and o.max_restarts == 20 and o.grid == 0
-    assert list(o.reserved) == [0] * 5
+    assert list(o.reserved) == [0] * 4
+    assert o.permute_domains == 1 and o.progress_every == 0
 
 
 def _setup(n, rowptr, colind, vals, part, t, s, **kw):
@@ -102,7 +103,7 @@ def test_setup_rejects(small, case):
     elif case == "nan_value":
         va[10] = np.nan
     elif case == "reserved":
-        kw = {"reserved": (ctypes.c_int32 * 5)(0, 0, 1, 0, 0)}
+        kw = {"reserved": (ctypes.c_int32 * 4)(0, 0, 1, 0)}
     elif case == "variant":
         kw = {"variant": 7}
     elif case == "inner_tol":

@@ -66,3 +66,67 @@ def test_sddmm_bit_exact(E):
     lam, x = rng.standard_normal(p.n), rng.standard_normal(p.n)
     g = sol.sddmm(lam, x).cpu().numpy()
     assert np.array_equal(g, O.sddmm(p.rowptr, p.colind, lam, x))
+
+
+@pytest.mark.parametrize("shape,parts,t", [((100, 100, 1), (2, 4, 1), 8),
+                                           ((37, 29, 5), (5, 3, 2), 30),
+                                           ((256, 256, 256), (4, 4, 4), 64)])
+def test_domain_order_bit_exact(E, shape, parts, t):
+    # the solver's domain-contiguous row order against the oracle's, for the
+    # caller's partition; the paper's 256^3 case included (order only: the
+    # matrix is a 7-point Laplacian of the same grid)
+    p = P.make_problem("lap", shape, P.kappa_constant(shape), seed=1, t=t, s=1, parts=parts) \
+        if shape[0] < 256 else None
+    dom = O.partition_grid(shape, parts)
+    if p is None:
+        # a diagonal matrix of the grid's size carries the partition
+        n = dom.shape[0]
+        rp, ci, va = np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n)
+    else:
+        rp, ci, va = p.rowptr, p.colind, p.vals
+    sol = E.Solver(rp, ci, va, dom, t, 1)
+    order = sol.domain_order().cpu().numpy()
+    assert np.array_equal(order, O.domain_order(dom))
+    sol.close()
+    sol0 = E.Solver(rp, ci, va, dom, t, 1, permute_domains=False)
+    assert np.array_equal(sol0.domain_order().cpu().numpy(), np.arange(dom.shape[0]))
+    sol0.close()
+
+
+def test_permuted_order_results_in_caller_order(E):
+    # every entry point returns the caller's order: T(r) bit-exact, SDDMM
+    # bit-exact, the product within rounding, and the solve within 1e-10
+    # of the one in the caller's order with the same iteration count
+    p = P.loguniform2d(40, t=8, parts=(2, 4, 1))
+    dom = O.partition_grid(p.shape, p.parts)
+    a = E.Solver(p.rowptr, p.colind, p.vals, dom, 8, 2)
+    b = E.Solver(p.rowptr, p.colind, p.vals, dom, 8, 2, permute_domains=False)
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal(p.n)
+    assert np.array_equal(a.tsplit(r).cpu().numpy(), O.split_T(r, dom, 8))
+    lam, x = rng.standard_normal(p.n), rng.standard_normal(p.n)
+    assert np.array_equal(a.sddmm(lam, x).cpu().numpy(), O.sddmm(p.rowptr, p.colind, lam, x))
+    X = rng.standard_normal((p.n, 5))
+    A = p.scipy()
+    bound = 8 * np.finfo(float).eps * (abs(A) @ np.abs(X))
+    assert (np.abs(a.spmm(X).cpu().numpy() - A @ X) <= bound + 1e-300).all()
+    a.close()
+    b.close()
+    # a well-conditioned system (the log-uniform one is rounding-sensitive:
+    # orders that differ only in rounding change its iteration count)
+    p = P.poisson2d(40, t=8, parts=(2, 4, 1))
+    A = p.scipy()
+    a = E.Solver(p.rowptr, p.colind, p.vals, dom, 8, 2)
+    b = E.Solver(p.rowptr, p.colind, p.vals, dom, 8, 2, permute_domains=False)
+    xa, ia = a.solve(p.b, tol=1e-10, maxit=2000)
+    xb, ib = b.solve(p.b, tol=1e-10, maxit=2000)
+    assert ia.status == ib.status == E.OK and ia.iters == ib.iters
+    xa, xb = xa.cpu().numpy(), xb.cpu().numpy()
+    assert np.linalg.norm(xa - xb) <= 1e-10 * np.linalg.norm(xb)
+    assert np.linalg.norm(p.b - A @ xa) <= 1e-10 * np.linalg.norm(p.b)
+    V, AV = a.basis()
+    V, AV = V.cpu().numpy(), AV.cpu().numpy()
+    assert np.abs(V.T @ (A @ V) - np.eye(V.shape[1])).max() <= 1e-10
+    assert np.abs(A @ V - AV).max() <= 1e-10 * np.abs(AV).max()
+    a.close()
+    b.close()

@@ -479,3 +479,18 @@ def test_parity_criterion_bounds_hold_for_oracle_ensembles():
     _, s2, sa = ensemble_spreads(runs, A)
     assert sa <= SPREAD_A and s2 <= SPREAD_2
     check_parity(runs[-1].iters, runs[-1].x, runs[:-1], A)
+
+
+def test_domain_order_brute_force():
+    # the definition written out: sort by (domain, row)
+    rng = np.random.default_rng(7)
+    for n, t in ((1, 1), (17, 3), (200, 8)):
+        dom = rng.integers(0, t, n).astype(np.int32)
+        want = sorted(range(n), key=lambda i: (int(dom[i]), i))
+        got = O.domain_order(dom)
+        assert got.dtype == np.int32 and got.tolist() == want
+    p = P.poisson2d(12, t=8, parts=(2, 4, 1))
+    dom = O.partition_grid(p.shape, p.parts)
+    order = O.domain_order(dom)
+    assert sorted(order.tolist()) == list(range(p.n))
+    assert (np.diff(dom[order]) >= 0).all()
