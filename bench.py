@@ -1,16 +1,31 @@
-"""Benchmark: time-to-1e-8 of s-step SRE-CG on one MI355X.
+"""Benchmark of the s-step enlarged CG hot path on one MI355X (gfx950).
 
-One step = one full solve (every s-step iteration, residual replacement
-included) of the heterogeneous 3D diffusion problem: 7-point stencil on a
-128^3 grid, kappa = 1 with full-height kappa = 1e5 columns on seeded 8x8
-tiles, t = 16 geometric domains (4 x 4 columns), s = 4, x* uniform in
-[-1, 1], b = A x*, x0 = 0, stop at a true relative residual of 1e-8.
-Inputs are resident in HBM before the timed region starts.
+Workload (default, --config C5): heterogeneous 3D diffusion, 7-point stencil
+on a 256^3 grid (n = 16,777,216, nnz = 117,047,296), kappa = 10^e on 32^3-cell
+blocks with e uniform in {0..6}, t = 64 box domains (4 x 4 x 4), s = 2,
+s-step SRE-CG (the short-recurrence variant), x* uniform in [-1, 1],
+b = A x*, x0 = 0, tolerance 1e-8 on the relative residual.  Inputs are
+resident in HBM before any timed region starts.
 
-Prints one JSON line.  Extra fields: the per-kernel algorithmic HBM
-bandwidth from HIP events recorded on the solver's stream during the timed
-steps, the same solve in the binary32-basis precision form, and the CPU
-oracle timed on a bounded sample.
+One step = one s-step iteration of the solve: s blocks (CGS2 against the two
+previous blocks, the sparse product with its Gram epilogue, A-CholQR), the
+x/r update and the residual norm.  W untimed steps (a solve stopped after W
+iterations), then K timed steps (a solve from x0 stopped after K iterations,
+bracketed by device synchronisations), with per-kernel timing switched off.
+value = HBM GB/s of those K iterations: the algorithmic bytes of every kernel
+they launch (operand bytes per launch, counted by the library) over the
+measured wall time.  The same is measured for the binary32-basis precision
+form.
+
+Time-to-1e-8 of the full solve: at 256^3 the solve takes about ten thousand
+s-step iterations (minutes), so it is measured by `python bench.py --full`
+(both forms, progress on stderr) and committed under profiles/; the default
+run measures the full time-to-1e-8 of the 128^3 skyscraper problem (t = 16,
+s = 4; seconds) in both forms as the `skyscraper_128` key.
+
+Extra keys: the kernel table and roofline of the dominant kernel (from a
+separate solve with per-kernel HIP events on the solver's stream), and the
+CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -19,6 +34,7 @@ import hashlib
 import json
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -28,7 +44,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-8 rel-residual + SpMM/block HBM GB/s; FP32-mixed vs FP64 solve"
-PEAK_HBM_GBS = 8000.0
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+PEAK_F64_MFMA_TFS = 78.6       # MI355X dense FP64 matrix
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1804_10629_amd", "csrc", "ecg_kernels.hip")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(msg):
@@ -37,29 +56,14 @@ def log(msg):
 
 def build_problem(cfg: str):
     import problems as P
-    maker = P.CONFIGS[cfg]
-    return maker()
+    return P.CONFIGS[cfg]()
 
 
-def timed_solves(E, solver, p, steps, warmup, tol, maxit):
-    import torch
-    bd = torch.as_tensor(p.b).cuda()
-    for i in range(warmup):
-        x, info = solver.solve(bd, tol=tol, maxit=maxit)
-        log(f"  warmup {i}: status {info.status} iters {info.iters} "
-            f"true relres {info.true_relres:.2e} {info.solve_ms:.1f} ms")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
-    for i in range(steps):
-        x, info = solver.solve(bd, tol=tol, maxit=maxit)
-        infos.append(info)
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / steps
-    for i, info in enumerate(infos):
-        log(f"  step {i}: status {info.status} iters {info.iters} restarts {info.restarts} "
-            f"true relres {info.true_relres:.2e} {info.solve_ms:.1f} ms")
-    return x, infos, wall
+def describe(p) -> str:
+    nx, ny, nz = p.shape
+    grid = f"{nx}x{ny}" if nz == 1 else f"{nx}x{ny}x{nz}"
+    return (f"{p.name} {grid} (n={p.n}, nnz={p.nnz}), s-step SRE-CG t={p.t} s={p.s}, "
+            f"tol {p.tol:g}")
 
 
 def kernel_table(stats):
@@ -73,13 +77,10 @@ def kernel_table(stats):
             "ms_total": round(ms, 3),
             "us_per_launch": round(1e3 * ms / v["launches"], 2),
             "gb_per_launch": round(v["bytes"] / v["launches"] / 1e9, 4),
+            "gflop_per_launch": round(v.get("flops", 0.0) / v["launches"] / 1e9, 3),
             "gbs": round(v["bytes"] / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
         }
     return out
-
-
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1804_10629_amd", "csrc", "ecg_kernels.hip")
-PROFILES = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_hash():
@@ -87,10 +88,10 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kclass, workload):
-    """HBM bytes per launch of a kernel class from the committed rocprofv3
+def measured_traffic(kclass, workload, form="fp64"):
+    """HBM bytes per launch of a kernel class from a committed rocprofv3
     --pmc summary (FETCH_SIZE and WRITE_SIZE, scaled against a plain copy),
-    or None when no summary matches this workload and kernel source."""
+    or None when no summary matches this workload, form and kernel source."""
     src = kernel_source_hash()
     if not os.path.isdir(PROFILES):
         return None
@@ -104,32 +105,171 @@ def measured_traffic(kclass, workload):
                     continue
                 d = json.loads(m.group(1))
                 if (d.get("kclass") == kclass and d.get("workload") == workload
+                        and d.get("form", "fp64") == form
                         and d.get("kernel_source_sha256_16") == src):
                     return d
     return None
 
 
-def cpu_baseline(p, gpu_iters, budget_iters=5):
+def roofline(ktab, workload, form):
+    """The dominant kernel class (device time) against its binding peak:
+    FP64 matrix cores when its flops at 78.6 TFLOP/s take longer than its
+    bytes at 8 TB/s, HBM otherwise."""
+    name = max(ktab, key=lambda k: ktab[k]["ms_total"])
+    k = ktab[name]
+    sec = k["us_per_launch"] * 1e-6
+    t_mem = k["gb_per_launch"] / PEAK_HBM_GBS
+    t_mfma = k["gflop_per_launch"] / (PEAK_F64_MFMA_TFS * 1e3)
+    tr = measured_traffic(name, workload, form)
+    common = {"kernel": name, "algorithmic_gb_per_launch": k["gb_per_launch"],
+              "gflop_per_launch": k["gflop_per_launch"],
+              "traffic": tr["hbm_gb_per_launch"] if tr else None,
+              "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+              "traffic_vs_algorithmic": (round(tr["hbm_gb_per_launch"] / k["gb_per_launch"], 3)
+                                         if tr else None),
+              "traffic_source": tr["file"] if tr else None}
+    if t_mfma > t_mem:
+        ach = k["gflop_per_launch"] / sec / 1e3
+        return {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAK_F64_MFMA_TFS,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_F64_MFMA_TFS, 4),
+                "hbm_gbs": round(k["gb_per_launch"] / sec, 1), **common}
+    ach = k["gb_per_launch"] / sec
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 4),
+            "tflops": round(k["gflop_per_launch"] / sec / 1e3, 2), **common}
+
+
+def host_info():
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["nproc"] = int(subprocess.run(["nproc"], capture_output=True, text=True,
+                                           timeout=10).stdout.strip())
+    except Exception:
+        pass
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        m = re.search(r"Model name:\s*(.+)", out)
+        if m:
+            info["cpu_model"] = m.group(1).strip()
+    except Exception:
+        pass
+    try:
+        with open("/proc/meminfo") as f:
+            m = re.search(r"MemTotal:\s*(\d+) kB", f.read())
+            if m:
+                info["mem_total_gb"] = round(int(m.group(1)) / 1e6, 1)
+    except Exception:
+        pass
+    return info
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def cpu_baseline(p, gpu_bytes_per_iter):
+    """The CPU oracle (as it stands) on the same problem, stopped after its
+    first basis block, timed; extrapolated to an s-step iteration (s blocks)
+    and expressed in the metric's unit with the GPU's bytes per iteration.
+    The first block has no CGS2 step, so this underestimates the oracle's
+    time per iteration."""
     import oracle as O
     A = p.scipy()
     dom = O.partition_grid(p.shape, p.parts)
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
-    r = O.sstep_srecg(A, dom, p.t, p.s, p.b, tol=p.tol, maxit=budget_iters)
+    r = O.sstep_srecg(A, dom, p.t, p.s, p.b, tol=p.tol, maxit=1, stop_after_blocks=1)
     dt = time.perf_counter() - t0
-    per_iter = dt / max(r.iters, 1)
+    per_iter = dt * p.s / max(r.blocks, 1)
+    hi = host_info()
     return {
-        "value": round(per_iter * gpu_iters, 2),
-        "unit": "s",
-        "cores": threads,
+        "value": round(gpu_bytes_per_iter / per_iter / 1e9, 3),
+        "unit": "GB/s",
+        "cores": blas_threads(),
         "kind": "oracle",
-        "sample": (f"{r.iters} s-step iteration(s) of the same problem ({per_iter:.2f} s each, "
-                   f"{r.iters * p.s} blocks), extrapolated to the GPU's {gpu_iters} iterations"),
+        "sample": (f"oracle (numpy/scipy, float64) on the same {p.shape[0]}^3 problem stopped "
+                   f"after its first basis block ({dt:.1f} s: T(r), the sparse product, the "
+                   f"Gram, Cholesky, two triangular solves); x {p.s} blocks = {per_iter:.1f} s "
+                   f"per s-step iteration (an underestimate: later blocks add CGS2), over the "
+                   f"GPU's algorithmic bytes per iteration; BLAS threads as 'cores', the "
+                   f"sparse product single-threaded"),
+        "s_per_iteration": round(per_iter, 2),
+        "host": hi,
     }
+
+
+def device_arrays(E, p):
+    import torch
+    dom = E.partition_grid(p.shape, p.parts)
+    rp = torch.as_tensor(p.rowptr).cuda()
+    ci = torch.as_tensor(p.colind).cuda()
+    va = torch.as_tensor(p.vals).cuda()
+    bd = torch.as_tensor(p.b).cuda()
+    return rp, ci, va, dom, bd
+
+
+def iteration_form(E, p, arrs, precision, steps, warmup, form):
+    """W untimed and K timed s-step iterations, then a separate K-iteration
+    solve with per-kernel events for the kernel table."""
+    import torch
+    rp, ci, va, dom, bd = arrs
+    t0 = time.perf_counter()
+    sol = E.Solver(rp, ci, va, dom, p.t, p.s, precision=precision)
+    torch.cuda.synchronize()
+    log(f"[{form}] setup {time.perf_counter() - t0:.1f} s")
+    if warmup > 0:
+        _, wi = sol.solve(bd, tol=p.tol, maxit=warmup)
+        log(f"[{form}] warmup: {wi.iters} iterations, rho/rho0 {wi.relres:.2e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info = sol.solve(bd, tol=p.tol, maxit=steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"[{form}] timed: {info.iters} iterations in {wall * 1e3:.1f} ms, "
+        f"rho/rho0 {info.relres:.2e}")
+    sol.close()
+    st = E.Solver(rp, ci, va, dom, p.t, p.s, precision=precision, collect_stats=True)
+    _, si = st.solve(bd, tol=p.tol, maxit=steps)
+    stats = st.stats()
+    st.close()
+    total_bytes = sum(v["bytes"] for v in stats.values())
+    return {"iters": info.iters, "wall_s": wall, "ms_per_step": wall * 1e3 / max(info.iters, 1),
+            "relres": info.relres, "bytes": total_bytes,
+            "gbs": total_bytes / wall / 1e9, "kernels": kernel_table(stats)}
+
+
+def full_solve(E, p, arrs, precision, maxit, form, progress_every=0):
+    """One warm-up solve of two iterations, then the full solve to the
+    tolerance, bracketed by device synchronisations."""
+    import torch
+    rp, ci, va, dom, bd = arrs
+    sol = E.Solver(rp, ci, va, dom, p.t, p.s, precision=precision,
+                   progress_every=progress_every)
+    sol.solve(bd, tol=p.tol, maxit=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info = sol.solve(bd, tol=p.tol, maxit=maxit)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sol.close()
+    xs = x.cpu().numpy()
+    log(f"[{form}] full solve: status {info.status}, {info.iters} iterations, "
+        f"{info.restarts} restarts, true relres {info.true_relres:.2e}, {wall:.2f} s")
+    return xs, {"time_s": round(wall, 4), "status": info.status, "iters": info.iters,
+                "restarts": info.restarts, "true_relres": info.true_relres,
+                "rel_err_vs_xstar": float(np.linalg.norm(xs - p.xstar) / np.linalg.norm(p.xstar))}
+
+
+def both_forms_to_tolerance(E, p, maxit, progress_every=0):
+    arrs = device_arrays(E, p)
+    x64, f64 = full_solve(E, p, arrs, E.FP64, maxit, "fp64", progress_every)
+    x32, mx = full_solve(E, p, arrs, E.MIXED, maxit, "mixed", progress_every)
+    mx["speedup_vs_fp64"] = round(f64["time_s"] / mx["time_s"], 3)
+    mx["rel_diff_vs_fp64_x"] = float(np.linalg.norm(x32 - x64) / np.linalg.norm(x64))
+    return {"workload": describe(p), "fp64": f64, "mixed": mx}
 
 
 def calibrate(torch):
@@ -156,18 +296,22 @@ def calibrate(torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="C2")
-    ap.add_argument("--maxit", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=20, help="timed s-step iterations")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed s-step iterations")
+    ap.add_argument("--config", default="C5", help="workload of the main line (C1..C5)")
+    ap.add_argument("--maxit", type=int, default=30000, help="bound for full solves")
+    ap.add_argument("--full", action="store_true",
+                    help="only the time-to-1e-8 of the main workload, both forms")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the full 128^3 skyscraper solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate", action="store_true",
                     help="time a plain 256 MiB device copy (the reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
-              "is a design, not a build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): every box has one GPU, "
+              "and the multi-GPU sharding is a design, not a build.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -179,82 +323,63 @@ def main():
         return
     t0 = time.perf_counter()
     p = build_problem(args.config)
-    log(f"problem {p.name}: n={p.n} nnz={p.nnz} t={p.t} s={p.s} ({time.perf_counter() - t0:.1f} s)")
-    dom = E.partition_grid(p.shape, p.parts)
-    rp = torch.as_tensor(p.rowptr).cuda()
-    ci = torch.as_tensor(p.colind).cuda()
-    va = torch.as_tensor(p.vals).cuda()
+    log(f"problem {describe(p)} ({time.perf_counter() - t0:.1f} s)")
+    if args.full:
+        res = both_forms_to_tolerance(E, p, args.maxit, progress_every=100)
+        print(json.dumps({"time_to_tolerance": res}), flush=True)
+        return
 
-    solver = E.Solver(rp, ci, va, dom, p.t, p.s, collect_stats=True)
-    log("FP64 solves")
-    x, infos, wall = timed_solves(E, solver, p, args.steps, args.warmup, p.tol, args.maxit)
-    info = infos[-1]
-    stats = solver.stats()     # kernels of the last timed solve
-    ktab = kernel_table(stats)
-    solver.close()
-
-    # dominant kernel class by device time: algorithmic bytes per launch over
-    # its mean launch time (HIP events on the solver's stream)
-    dom_name = max(ktab, key=lambda k: ktab[k]["ms_total"])
-    dk = ktab[dom_name]
-    achieved = dk["gb_per_launch"] / (dk["us_per_launch"] * 1e-6)
-    tr = measured_traffic(dom_name, p.name)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": tr["hbm_gb_per_launch"] if tr else None,
-                "kernel": dom_name, "algorithmic_gb_per_launch": dk["gb_per_launch"],
-                "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                "traffic_vs_algorithmic": (round(tr["hbm_gb_per_launch"] / dk["gb_per_launch"], 3)
-                                           if tr else None),
-                "traffic_source": tr["file"] if tr else None}
-
+    arrs = device_arrays(E, p)
+    main_f = iteration_form(E, p, arrs, E.FP64, args.steps, args.warmup, "fp64")
     mixed = None
     if not args.no_mixed:
-        log("mixed-precision solves")
-        ms = E.Solver(rp, ci, va, dom, p.t, p.s, precision=E.MIXED, collect_stats=True)
-        xm, minfos, mwall = timed_solves(E, ms, p, args.steps, args.warmup, p.tol, args.maxit)
-        mi = minfos[-1]
-        xm_np, x_np = xm.cpu().numpy(), x.cpu().numpy()
-        mixed = {
-            "time_s": round(mwall, 4), "iters": mi.iters, "restarts": mi.restarts,
-            "status": mi.status, "true_relres": mi.true_relres,
-            "speedup_vs_fp64": round(wall / mwall, 3),
-            "rel_diff_vs_fp64_x": float(np.linalg.norm(xm_np - x_np) / np.linalg.norm(x_np)),
-            "rel_err_vs_xstar": float(np.linalg.norm(xm_np - p.xstar) / np.linalg.norm(p.xstar)),
-            "kernels": kernel_table(ms.stats()),
-        }
-        ms.close()
+        mixed = iteration_form(E, p, arrs, E.MIXED, args.steps, args.warmup, "mixed")
+    del arrs
+    torch.cuda.empty_cache()
+
+    sky = None
+    if not args.no_solve:
+        ps = build_problem("C2")
+        log(f"problem {describe(ps)}")
+        sky = both_forms_to_tolerance(E, ps, args.maxit)
 
     cpu = None
+    bytes_per_iter = main_f["bytes"] / max(main_f["iters"], 1)
     if not args.no_cpu_baseline:
         log("CPU oracle sample")
-        cpu = cpu_baseline(p, info.iters)
+        cpu = cpu_baseline(p, bytes_per_iter)
 
-    xs = x.cpu().numpy()
     out = {
         "metric": METRIC,
-        "value": round(wall, 4),
-        "unit": "s",
+        "value": round(main_f["gbs"], 1),
+        "unit": "GB/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": main_f["iters"],
         "warmup": args.warmup,
-        "ms_per_step": round(wall * 1e3, 2),
-        "higher_is_better": False,
-        "scaling": "strong",
+        "ms_per_step": round(main_f["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{p.name} {p.shape[0]}x{p.shape[1]}x{p.shape[2]} "
-                               f"(n={p.n}, nnz={p.nnz}), s-step SRE-CG t={p.t} s={p.s}, tol {p.tol:g}",
-                   "n": p.n, "nnz": p.nnz, "t": p.t, "s": p.s, "tol": p.tol,
-                   "variant": "s-step SRE-CG", "parallelism": "single GPU"},
-        "iters": info.iters,
-        "restarts": info.restarts,
-        "true_relres": info.true_relres,
-        "rel_err_vs_xstar": float(np.linalg.norm(xs - p.xstar) / np.linalg.norm(p.xstar)),
-        "kernels": ktab,
-        "roofline": roofline,
-        "mixed": mixed,
+        "config": {"workload": describe(p), "n": p.n, "nnz": p.nnz, "t": p.t, "s": p.s,
+                   "tol": p.tol, "variant": "s-step SRE-CG", "parallelism": "single GPU",
+                   "step": "one s-step iteration"},
+        "value_definition": ("algorithmic HBM bytes of the kernels of the timed s-step "
+                             "iterations over their wall time (binary64)"),
+        "gb_per_step": round(bytes_per_iter / 1e9, 3),
+        "kernels": main_f["kernels"],
+        "roofline": roofline(main_f["kernels"], p.name, "fp64"),
+        "mixed": None if mixed is None else {
+            "value": round(mixed["gbs"], 1), "unit": "GB/s",
+            "ms_per_step": round(mixed["ms_per_step"], 3),
+            "speedup_per_step_vs_fp64": round(main_f["ms_per_step"] / mixed["ms_per_step"], 3),
+            "gb_per_step": round(mixed["bytes"] / max(mixed["iters"], 1) / 1e9, 3),
+            "kernels": mixed["kernels"],
+            "roofline": roofline(mixed["kernels"], p.name, "mixed"),
+        },
+        "time_to_1e8": {"source": "python bench.py --full (profiles/)", "in_this_run": False},
+        "skyscraper_128": sky,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

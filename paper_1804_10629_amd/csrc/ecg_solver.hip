@@ -852,8 +852,9 @@ struct Engine {
       ka.tail.rinv_p2 = np == 2 ? rinv(p2) : nullptr;
       set_fold(ka, fold);
       Timed tm;
+      // update with np + 1 operands, np Grams (2 n t^2 flops each)
       c->tstart(tm, ECG_K_CGS_GRAM, (2.0 * np + 1.0) * bb + (fold ? 32.0 * c->n : 0.0),
-                2.0 * nt2 * (2 * np + 1 + np));
+                2.0 * nt2 * ((np + 1) + np) + (fold ? 4.0 * c->n * c->t : 0.0));
       HIP_TRY((launch_update_gram<TPI, S>(np + 1, np, false, true, TAIL_CGS, ka, c->grid, c->st)));
       c->tstop(tm);
       int rc = reduce(gram_partials(TPI, c->grid), np * TPI * TPI, TAIL_CGS, np, ka.tail);
@@ -894,8 +895,12 @@ struct Engine {
     sa.tail.beta = beta(slot);
     Timed tm;
     const int vb = std::is_same<SA, float>::value ? 4 : 8;
+    // algorithmic flops: the product, the upper triangles of the symmetric
+    // Grams G and F (n t (t + 1) each), E in full, a = Z^t r
+    const double ntt1 = (double)c->n * c->t * (c->t + 1);
     c->tstart(tm, ECG_K_SPMM, c->csr_bytes(vb) + (m >= 2 ? 3.0 : 2.0) * bb + 8.0 * c->n,
-              2.0 * c->nnz * c->t + 2.0 * nt2 * (m >= 2 ? 3 : 2) + 2.0 * c->n * c->t);
+              2.0 * c->nnz * c->t + 2.0 * ntt1 + (m >= 2 ? 2.0 * nt2 : 0.0) +
+                  2.0 * c->n * c->t);
     HIP_TRY((launch_spmm<TPI, S, SA>(true, m >= 2, TAIL_SPMM, sa, c->grid, c->st)));
     c->tstop(tm);
     return reduce(gram_partials(TPI, c->grid), 3 * TPI * TPI + TPI, TAIL_SPMM, 0, sa.tail);
