@@ -12,24 +12,20 @@ namespace ecg {
 constexpr int kThreads = 256;     // threads per work-group of the block kernels
 constexpr int kMaxS = 16;         // largest s supported by the x/r update
 
-// Blocks of at least ECG_CS_MIN_TPI stored columns (64: at 32 the
-// row-per-lane-group kernels are faster) use the column-split product
-// kernel (row groups of four waves, each writing its own Gram partial;
-// cs_threads(TPI) threads per work-group: one row group, which measured
-// faster than two) and the matrix-core block update (work-groups of four
-// waves, one partial each), both launched with kCSGroups row groups per
-// unit of the grid, so both write gram_partials(TPI, grid) partials.
+// 64-column blocks use the matrix-core block update with kCSGroups
+// work-groups (one Gram partial each) per unit of the grid, and the 64-column
+// product kernels (see launch_spmm).
 #ifndef ECG_CS_MIN_TPI
 #define ECG_CS_MIN_TPI 64
 #endif
 constexpr int kCSGroups = 2;
-#ifndef ECG_CS_THREADS64
-#define ECG_CS_THREADS64 256
-#endif
-constexpr int cs_threads(int tpi) { return tpi == 64 ? ECG_CS_THREADS64 : 256; }
 constexpr bool uses_cs(int tpi) { return tpi >= ECG_CS_MIN_TPI; }
 // Gram partials written by a launch of `grid` work-groups.
 constexpr int gram_partials(int tpi, int grid) { return uses_cs(tpi) ? grid * kCSGroups : grid; }
+// Gram partials written by the product kernel with Grams (launch_spmm), and
+// the compute units of the current device.
+int spmm_partials(int tpi, int grid, int max_row);
+int device_cus();
 
 // Deterministic reduction over work-groups: every work-group of a streaming
 // kernel writes its partial vector; k_reduce_groups then sums groups of
@@ -109,6 +105,7 @@ struct SpArgs {
   const S* AZprev;      // A-image of the previous block (E Gram), nullable
   const double* rvec;   // residual for a = Z^t r, nullable
   int64_t n;
+  int max_row;          // most entries in a row of the matrix
   RedCtl rc;
   TailArgs tail;
 };

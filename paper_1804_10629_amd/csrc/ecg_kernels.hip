@@ -9,18 +9,24 @@
 // resp. j + 16 k), so tall-skinny Gram products P^t Q = sum_rows P[r]^t Q[r]
 // feed loaded registers straight into MFMA.  The 16 x 16 result D comes
 // back with D[4 v + l / 16][l % 16] in element v of lane l.
-// The block update out[r] = sum_b X_b[r] C_b (C_b small, t x t) runs on the
-// FP64 VALU, broadcasting X_b[r][k] across its DPP row (row_newbcast) and
-// reading C_b from LDS.
+// Block updates out[r] = sum_b X_b[r] C_b (C_b small, t x t) run on the
+// matrix cores (k_update_gram_mf), except the 16-column binary64 updates
+// without Grams, which stream on the FP64 VALU (k_update_gram): X_b[r][k]
+// broadcast across its DPP row (row_newbcast), C_b read from LDS.  The
+// product kernels gather the rows of the block that A's pattern selects and
+// fold the Grams of A-CholQR and of the next block's first CGS pass into
+// their epilogue.
 //
-// Reductions never use floating-point atomics: work-group partials are
-// combined by a fixed-order two-level tree (RedCtl), so results are
-// bitwise reproducible run to run.  The last work-group then runs the small
-// dense algebra (Cholesky of the t x t Gram, R^{-1}, the next block's CGS
-// coefficients) so no host round trip is needed between blocks.
+// Reductions never use floating-point atomics: every work-group writes its
+// partial, and two small kernels after the producer (k_reduce_groups, then
+// k_final in one work-group) sum them in a fixed index order and run the
+// small dense algebra (Cholesky of the t x t Gram, R^{-1}, the next block's
+// CGS coefficients) on the device, so results are bitwise reproducible run
+// to run and no host round trip is needed between blocks.
 
 #include "ecg_kernels.h"
 
+#include <algorithm>
 #include <type_traits>
 #include <utility>
 
@@ -96,8 +102,10 @@ __device__ __forceinline__ T opaque(T v) {
 }
 
 // Tuning knobs (compile-time): row quads per lane of the block-update
-// kernels at TPI = 16 / 32, prefetch of the next step's operands, row quads
-// per lane and gather chunk of the product kernel.
+// kernels at TPI = 16 / 32, prefetch of the next step's operands, which
+// block updates run on the matrix cores, rows per step of the product and
+// x/r kernels.  The defaults are the measured fastest; every kernel they
+// select between is also used by default for some block width.
 #ifndef ECG_UG_RPL16
 #define ECG_UG_RPL16 4
 #endif
@@ -106,9 +114,6 @@ __device__ __forceinline__ T opaque(T v) {
 #endif
 #ifndef ECG_UG_PREFETCH
 #define ECG_UG_PREFETCH 0
-#endif
-#ifndef ECG_SP_RPL16
-#define ECG_SP_RPL16 4
 #endif
 #ifndef ECG_XCD_MAP
 #define ECG_XCD_MAP 1
@@ -146,20 +151,8 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #ifndef ECG_F32_RPL_MUL
 #define ECG_F32_RPL_MUL 2      // row-quad multiplier of the update kernels for binary32 blocks
 #endif
-#ifndef ECG_F32_SP_RPL_MUL
-#define ECG_F32_SP_RPL_MUL 1   // the same for the product kernel
-#endif
 #ifndef ECG_UG_CGROUP
 #define ECG_UG_CGROUP 4        // coefficient rows read from LDS per group (divides 16)
-#endif
-#ifndef ECG_SP_CHUNK
-#define ECG_SP_CHUNK 8
-#endif
-#ifndef ECG_SP_OFF32
-#define ECG_SP_OFF32 0         // 32-bit gather offsets when the block spans < 4 GiB
-#endif
-#ifndef ECG_SP_WIDE
-#define ECG_SP_WIDE 1          // wide-gather product kernel for 16-column binary64 blocks
 #endif
 #ifndef ECG_MF32
 #define ECG_MF32 1             // 32-column block updates on the matrix cores as well
@@ -182,36 +175,11 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 #ifndef ECG_XR_RQ
 #define ECG_XR_RQ 4            // row sets per step of that kernel
 #endif
-#ifndef ECG_SPW32
-#define ECG_SPW32 1            // wide-gather product kernels for 32-column blocks
-#endif
 #ifndef ECG_SPW32_RQ
 #define ECG_SPW32_RQ 2         // row quads per step of that kernel
 #endif
-#ifndef ECG_CS_ZLDS
-#define ECG_CS_ZLDS 1          // column-split product: Z and A Z_prev column blocks via LDS
-#endif
 #ifndef ECG_SPWF_RQ
 #define ECG_SPWF_RQ 1          // 16-row sets per step of the binary32 wide-gather kernel
-#endif
-#ifndef ECG_SP_DEEP
-#define ECG_SP_DEEP 1          // deeper-pipelined product kernel at 16 columns: 1 for
-                               // binary32 blocks (faster there), 2 always, 0 never
-#endif
-#ifndef ECG_SP_DRPL
-#define ECG_SP_DRPL 2          // its row quads per lane
-#endif
-#ifndef ECG_CS_RPL
-#define ECG_CS_RPL 2           // row quads per lane of the column-split kernels
-#endif
-#ifndef ECG_CS_WPE
-#define ECG_CS_WPE 2
-#endif
-#ifndef ECG_P64
-#define ECG_P64 1              // 64-column product kernel with upper-triangle Grams
-#endif
-#ifndef ECG_P64_MAP
-#define ECG_P64_MAP 0          // its step mapping (p64_steps)
 #endif
 
 
@@ -986,204 +954,6 @@ __global__ ECG_STREAM void k_update_gram(UGArgs<S> a) {
   }
 }
 
-// AZ = A Z (row by row) with the Gram epilogue G = Z^t AZ, F = AZ^t AZ,
-// E = AZprev^t AZ and a = Z^t r.
-constexpr int kChunk = ECG_SP_CHUNK;   // <= 16
-
-template <int TPI, typename S = double>
-struct SpCfg {
-  static constexpr int EPL = TPI / 16;
-  static constexpr int RPL = (TPI == 16 ? ECG_SP_RPL16 : (TPI == 32 ? 2 : 1)) *
-                             (sizeof(S) == 4 ? ECG_F32_SP_RPL_MUL : 1);
-  static constexpr int WROWS = 4 * RPL;
-  static constexpr int NWAVE = kThreads / 64;
-  static constexpr int WGROWS = WROWS * NWAVE;
-};
-
-// OFF32: the block spans less than 4 GiB, so gathered rows are addressed by
-// a 32-bit byte offset from the block's base (one register per address).
-template <int TPI, typename S, typename SA, bool GRAMS, bool HAS_PREV, int TAIL, bool OFF32>
-__global__ ECG_SPMM_ATTR void k_spmm(SpArgs<S, SA> a) {
-  using C = SpCfg<TPI, S>;
-  constexpr int EPL = C::EPL, RPL = C::RPL, T2 = TPI * TPI;
-  constexpr int L = 3 * T2 + TPI;
-  constexpr int LDSN = GRAMS ? L : 1;
-  __shared__ double lds[LDSN];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m = lane & 15, rq = lane >> 4;
-
-  d4 accG[EPL][EPL], accF[EPL][EPL], accE[EPL][EPL];
-  double av[EPL];
-  for (int i = 0; i < EPL; ++i) {
-    av[i] = 0.0;
-    for (int j = 0; j < EPL; ++j) {
-      accG[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      accF[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      accE[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-    }
-  }
-  const int64_t n = a.n;
-  const int nnz_last = a.rowptr[n] - 1;
-  const Steps sp = my_steps((n + C::WGROWS - 1) / C::WGROWS);
-
-  // Software pipeline over the wave's steps: while the rows of step i are
-  // gathered, the first kChunk (column, value) pairs of step i+1 and the
-  // row pointers of step i+2 are in flight, so a step waits on one memory
-  // round trip instead of three dependent ones.
-  struct RowPtr {
-    int p0[RPL], p1[RPL];
-  };
-  struct Head {                 // first chunk of every row: lane m holds entry m % kChunk
-    double offb[OFF32 ? 1 : RPL], valb[RPL];
-    int offw[OFF32 ? RPL : 1];
-  };
-  auto load_rowptr = [&](int64_t step, RowPtr& rp) {
-    const int64_t row0 = step * C::WGROWS + wave * C::WROWS + rq;
-    for (int q = 0; q < RPL; ++q) {
-      // rows past the end take row n-1's entries; their results are masked
-      const int64_t row = row0 + 4 * q;
-      const int64_t rc = row < n ? row : n - 1;
-      rp.p0[q] = ld_s(a.rowptr + rc);
-      rp.p1[q] = ld_s(a.rowptr + rc + 1);
-    }
-  };
-  auto load_chunk = [&](const RowPtr& rp, int c, Head& h) {
-    for (int q = 0; q < RPL; ++q) {
-      const int idx = rp.p0[q] + c + (m % kChunk);
-      const int idc = min(idx, nnz_last);
-      const int64_t msk = opaque((int64_t)(idx < rp.p1[q] ? -1 : 0));
-      const double okf = opaque(idx < rp.p1[q] ? 1.0 : 0.0);
-      const int64_t col = ld_s(a.colind + idc);
-      if constexpr (OFF32)
-        h.offw[q] = (int)(((uint32_t)col * (uint32_t)(TPI * sizeof(S))) & (uint32_t)msk);
-      else
-        h.offb[q] = __builtin_bit_cast(double, (int64_t)(col * TPI) & msk);
-      h.valb[q] = static_cast<double>(ld_s(a.vals + idc)) * okf;
-    }
-  };
-  auto gather = [&](const Head& h, double (&y)[RPL][EPL]) {
-    static_for<kChunk>([&](auto jc) {
-      constexpr int j = decltype(jc)::value;
-      for (int q = 0; q < RPL; ++q) {
-        const double vj = bcast64<j>(h.valb[q]);
-        const S* zr;
-        if constexpr (OFF32) {
-          const uint32_t off = (uint32_t)bcast32<j>(h.offw[q]) + (uint32_t)(m * sizeof(S));
-          zr = (const S*)((const char*)a.Z + (size_t)off);
-        } else {
-          zr = a.Z + __builtin_bit_cast(int64_t, bcast64<j>(h.offb[q])) + m;
-        }
-        for (int e = 0; e < EPL; ++e) y[q][e] = __builtin_fma(vj, ld(zr + 16 * e), y[q][e]);
-      }
-    });
-  };
-
-  RowPtr rp_cur, rp_nxt;
-  Head h_cur;
-  int64_t step = sp.first;
-  if (step < sp.end) {
-    load_rowptr(step, rp_cur);
-    load_chunk(rp_cur, 0, h_cur);
-    if (step + sp.stride < sp.end) load_rowptr(step + sp.stride, rp_nxt);
-  }
-  for (; step < sp.end; step += sp.stride) {
-    const int64_t s1 = step + sp.stride, s2 = s1 + sp.stride;
-    const bool has1 = s1 < sp.end, has2 = s2 < sp.end;
-    Head h_nxt;
-    RowPtr rp_nn;
-    if (has1) load_chunk(rp_nxt, 0, h_nxt);
-    if (has2) load_rowptr(s2, rp_nn);
-
-    const int64_t row0 = step * C::WGROWS + wave * C::WROWS + rq;
-    int64_t rowc[RPL];
-    bool ok[RPL];
-    double okf[RPL];
-    int len = 0;
-    for (int q = 0; q < RPL; ++q) {
-      const int64_t row = row0 + 4 * q;
-      ok[q] = row < n;
-      rowc[q] = ok[q] ? row : n - 1;
-      okf[q] = opaque(ok[q] ? 1.0 : 0.0);
-      len = max(len, rp_cur.p1[q] - rp_cur.p0[q]);
-    }
-    // operands of the Gram epilogue, independent of the product (rvec is
-    // always given with the Grams)
-    double z[RPL][EPL], pz[RPL][EPL], rv[RPL];
-    if constexpr (GRAMS) {
-      for (int q = 0; q < RPL; ++q) {
-        rv[q] = ld_s(a.rvec + rowc[q]) * okf[q];
-        for (int e = 0; e < EPL; ++e) {
-          z[q][e] = ld(a.Z + rowc[q] * TPI + m + 16 * e) * okf[q];
-          if constexpr (HAS_PREV)
-            pz[q][e] = static_cast<double>(ld_s(a.AZprev + rowc[q] * TPI + m + 16 * e)) * okf[q];
-          else pz[q][e] = 0.0;
-        }
-      }
-    }
-    double y[RPL][EPL];
-    for (int q = 0; q < RPL; ++q)
-      for (int e = 0; e < EPL; ++e) y[q][e] = 0.0;
-    gather(h_cur, y);
-    for (int c = kChunk; c < len; c += kChunk) {   // rows longer than one chunk
-      Head h;
-      load_chunk(rp_cur, c, h);
-      gather(h, y);
-    }
-    for (int q = 0; q < RPL; ++q)
-      if (ok[q])
-        for (int e = 0; e < EPL; ++e) st_s(a.AZ + rowc[q] * TPI + m + 16 * e, static_cast<S>(y[q][e]));
-    if constexpr (GRAMS) {
-      for (int q = 0; q < RPL; ++q) {
-        for (int e = 0; e < EPL; ++e) {
-          // the stored (rounded) value of AZ enters the Grams; rows past
-          // the end contribute nothing
-          y[q][e] = static_cast<double>(static_cast<S>(y[q][e])) * okf[q];
-        }
-        for (int i = 0; i < EPL; ++i) {
-          av[i] = __builtin_fma(z[q][i], rv[q], av[i]);
-          for (int j = 0; j < EPL; ++j) {
-            accG[i][j] = mfma16(z[q][i], y[q][j], accG[i][j]);
-            accF[i][j] = mfma16(y[q][i], y[q][j], accF[i][j]);
-            if constexpr (HAS_PREV) accE[i][j] = mfma16(pz[q][i], y[q][j], accE[i][j]);
-          }
-        }
-      }
-    }
-    if (has1) {
-      h_cur = h_nxt;
-      rp_cur = rp_nxt;
-    }
-    if (has2) rp_nxt = rp_nn;
-  }
-  if constexpr (GRAMS) {
-    // a: reduce over the four row lanes of each column, then over waves
-    for (int i = 0; i < EPL; ++i) {
-      av[i] += __shfl_xor(av[i], 16, 64);
-      av[i] += __shfl_xor(av[i], 32, 64);
-    }
-    for (int w = 0; w < C::NWAVE; ++w) {
-      if (wave == w) {
-        for (int i = 0; i < EPL; ++i)
-          for (int j = 0; j < EPL; ++j)
-            for (int v = 0; v < 4; ++v) {
-              const int idx = (16 * i + 4 * v + rq) * TPI + 16 * j + m;
-              const bool first = (w == 0);
-              lds[idx] = (first ? 0.0 : lds[idx]) + accG[i][j][v];
-              lds[T2 + idx] = (first ? 0.0 : lds[T2 + idx]) + accF[i][j][v];
-              lds[2 * T2 + idx] = (first ? 0.0 : lds[2 * T2 + idx]) + accE[i][j][v];
-            }
-        if (rq == 0)
-          for (int i = 0; i < EPL; ++i) {
-            const int idx = 3 * T2 + 16 * i + m;
-            lds[idx] = (w == 0 ? 0.0 : lds[idx]) + av[i];
-          }
-      }
-      __syncthreads();
-    }
-    write_partial(lds, L, a.rc);
-  }
-}
-
 // Wide-gather product kernel for 16-column binary64 blocks.  The gathers
 // dominate the kernel's vector-memory instructions and its address unit is
 // the busy resource, so rows are gathered 16 bytes per lane: 8 lanes per
@@ -1888,270 +1658,6 @@ __global__ ECG_SPMM_ATTR void k_spmm_widef(SpArgs<float, float> a) {
   }
 }
 
-// Deeper pipeline for the product kernel: while step i is summed, the
-// gathers of step i+1, the first chunk of step i+2 and the row pointers of
-// step i+3 are in flight, so two steps of gathered rows are outstanding per
-// wave.  Every stage keeps two buffers indexed by the step's parity and the
-// loop is unrolled by two, so that no loaded register is copied (a copy
-// would wait for the load); loaded values stay raw until the step that
-// uses them for the same reason.
-template <int TPI, typename S, typename SA, bool GRAMS, bool HAS_PREV>
-__global__ ECG_SPMM_ATTR void k_spmm_deep(SpArgs<S, SA> a) {
-  constexpr int EPL = TPI / 16, RPL = ECG_SP_DRPL, T2 = TPI * TPI;
-  constexpr int WROWS = 4 * RPL, NWAVE = kThreads / 64, WGROWS = WROWS * NWAVE;
-  constexpr int L = 3 * T2 + TPI;
-  constexpr int LDSN = GRAMS ? L : 1;
-  __shared__ double lds[LDSN];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m = lane & 15, rq = lane >> 4;
-
-  d4 accG[EPL][EPL], accF[EPL][EPL], accE[EPL][EPL];
-  double av[EPL];
-  for (int i = 0; i < EPL; ++i) {
-    av[i] = 0.0;
-    for (int j = 0; j < EPL; ++j) {
-      accG[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      accF[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      accE[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-    }
-  }
-  const int64_t n = a.n;
-  const int nnz_last = a.rowptr[n] - 1;
-  const Steps sp = my_steps((n + WGROWS - 1) / WGROWS);
-
-  struct RowPtr {
-    int p0[RPL], p1[RPL];
-  };
-  struct Head {              // first chunk of a step and the step's row pointers
-    int col[RPL];
-    SA val[RPL];
-    int p0[RPL], p1[RPL];
-  };
-  struct Gath {
-    double v[kChunk][RPL][EPL];
-  };
-  struct Ops {
-    double z[RPL][EPL], pz[RPL][EPL], rv[RPL];
-  };
-  auto row_of = [&](int64_t step, int q) { return step * WGROWS + wave * WROWS + rq + 4 * q; };
-  auto load_rowptr = [&](int64_t step, RowPtr& rp) {
-    for (int q = 0; q < RPL; ++q) {
-      const int64_t row = row_of(step, q);
-      const int64_t rc = row < n ? row : n - 1;
-      rp.p0[q] = ld_s(a.rowptr + rc);
-      rp.p1[q] = ld_s(a.rowptr + rc + 1);
-    }
-  };
-  auto load_head = [&](const RowPtr& rp, Head& h) {
-    for (int q = 0; q < RPL; ++q) {
-      h.p0[q] = rp.p0[q];
-      h.p1[q] = rp.p1[q];
-      const int idc = min(rp.p0[q] + (m % kChunk), nnz_last);
-      h.col[q] = ld_s(a.colind + idc);
-      h.val[q] = ld_s(a.vals + idc);
-    }
-  };
-  // chunk c of step h: offsets and values with entries past the row masked
-  auto chunk_ov = [&](const Head& h, int c, const int (&col)[RPL], const SA (&val)[RPL],
-                      double (&offb)[RPL], double (&valb)[RPL]) {
-    for (int q = 0; q < RPL; ++q) {
-      const bool ok = h.p0[q] + c + (m % kChunk) < h.p1[q];
-      const int64_t msk = opaque((int64_t)(ok ? -1 : 0));
-      offb[q] = __builtin_bit_cast(double, ((int64_t)col[q] * TPI) & msk);
-      valb[q] = static_cast<double>(val[q]) * opaque(ok ? 1.0 : 0.0);
-    }
-  };
-  auto issue_gather = [&](const double (&offb)[RPL], Gath& g) {
-    static_for<kChunk>([&](auto jc) {
-      constexpr int j = decltype(jc)::value;
-      for (int q = 0; q < RPL; ++q) {
-        const int64_t off = __builtin_bit_cast(int64_t, bcast64<j>(offb[q]));
-        for (int e = 0; e < EPL; ++e) g.v[j][q][e] = ld(a.Z + off + m + 16 * e);
-      }
-    });
-  };
-  auto consume = [&](const double (&valb)[RPL], const Gath& g, double (&y)[RPL][EPL]) {
-    static_for<kChunk>([&](auto jc) {
-      constexpr int j = decltype(jc)::value;
-      for (int q = 0; q < RPL; ++q) {
-        const double vj = bcast64<j>(valb[q]);
-        for (int e = 0; e < EPL; ++e) y[q][e] = __builtin_fma(vj, g.v[j][q][e], y[q][e]);
-      }
-    });
-  };
-  auto load_ops = [&](int64_t step, Ops& o) {
-    if constexpr (GRAMS) {
-      for (int q = 0; q < RPL; ++q) {
-        const int64_t row = row_of(step, q);
-        const int64_t rc = row < n ? row : n - 1;
-        o.rv[q] = ld_s(a.rvec + rc);
-        for (int e = 0; e < EPL; ++e) {
-          o.z[q][e] = ld(a.Z + rc * TPI + m + 16 * e);
-          if constexpr (HAS_PREV)
-            o.pz[q][e] = static_cast<double>(ld_s(a.AZprev + rc * TPI + m + 16 * e));
-          else
-            o.pz[q][e] = 0.0;
-        }
-      }
-    }
-  };
-
-  const int64_t S0 = sp.first, SD = sp.stride, SE = sp.end;
-  RowPtr rp[2];
-  Head hd[2];
-  Gath g[2];
-  Ops o[2];
-  // Steps past the end are loaded like the others (their rows are clamped
-  // to n-1 and never stored): conditional loads would make the wait after
-  // the join cover every outstanding load.
-  // Order within the body of step i: (a) values of step i from its head;
-  // (b) row pointers of step i+3 and the head of step i+2 (addresses known
-  // from loads of the previous body that precede its gathers); (c) gathers
-  // of step i+1; (d) sum of step i, whose wait leaves (b) and (c) in flight.
-  // prologue: heads of steps 0 and 1, row pointers of step 2, gathers of step 0
-  if (S0 < SE) {
-    load_rowptr(S0, rp[0]);
-    load_rowptr(S0 + SD, rp[1]);
-    load_head(rp[0], hd[0]);
-    load_head(rp[1], hd[1]);
-    load_rowptr(S0 + 2 * SD, rp[0]);
-    double offb[RPL], valb[RPL];
-    chunk_ov(hd[0], 0, hd[0].col, hd[0].val, offb, valb);
-    issue_gather(offb, g[0]);
-    load_ops(S0, o[0]);
-  }
-  // one step with the buffers of parity P (step i) and 1-P (step i+1)
-  auto body = [&](auto pc, int64_t step) {
-    constexpr int P = decltype(pc)::value, Q = 1 - P;
-    // (a) step i's values from its head, which is then free
-    double valb_i[RPL];
-    int p0_i[RPL], p1_i[RPL];
-    {
-      double offb[RPL];
-      chunk_ov(hd[P], 0, hd[P].col, hd[P].val, offb, valb_i);
-      for (int q = 0; q < RPL; ++q) {
-        p0_i[q] = hd[P].p0[q];
-        p1_i[q] = hd[P].p1[q];
-      }
-    }
-    // (b) head of step i+2 (row pointers in rp[P]), row pointers of step i+3
-    load_head(rp[P], hd[P]);
-    load_rowptr(step + 3 * SD, rp[Q]);
-    // (c) gathers and Gram operands of step i+1
-    {
-      double offb[RPL], valb[RPL];
-      chunk_ov(hd[Q], 0, hd[Q].col, hd[Q].val, offb, valb);
-      issue_gather(offb, g[Q]);
-      load_ops(step + SD, o[Q]);
-    }
-    // (d) step i
-    double y[RPL][EPL];
-    for (int q = 0; q < RPL; ++q)
-      for (int e = 0; e < EPL; ++e) y[q][e] = 0.0;
-    consume(valb_i, g[P], y);
-    int len = 0;
-    for (int q = 0; q < RPL; ++q) len = max(len, p1_i[q] - p0_i[q]);
-    for (int c = kChunk; c < len; c += kChunk) {   // rows longer than one chunk
-      Head hx;
-      for (int q = 0; q < RPL; ++q) {
-        hx.p0[q] = p0_i[q];
-        hx.p1[q] = p1_i[q];
-        const int idc = min(p0_i[q] + c + (m % kChunk), nnz_last);
-        hx.col[q] = ld_s(a.colind + idc);
-        hx.val[q] = ld_s(a.vals + idc);
-      }
-      double offb[RPL], valb[RPL];
-      chunk_ov(hx, c, hx.col, hx.val, offb, valb);
-      Gath gx;
-      issue_gather(offb, gx);
-      consume(valb, gx, y);
-    }
-    double okf[RPL];
-    for (int q = 0; q < RPL; ++q) {
-      const int64_t row = row_of(step, q);
-      okf[q] = opaque(row < n ? 1.0 : 0.0);
-      if (row < n)
-        for (int e = 0; e < EPL; ++e) st_s(a.AZ + row * TPI + m + 16 * e, static_cast<S>(y[q][e]));
-    }
-    if constexpr (GRAMS) {
-      for (int q = 0; q < RPL; ++q) {
-        // y is zero on rows past the end, which masks every Gram; a = Z^t r
-        // takes the mask itself
-        for (int e = 0; e < EPL; ++e) y[q][e] = static_cast<double>(static_cast<S>(y[q][e])) * okf[q];
-        for (int i = 0; i < EPL; ++i) {
-          av[i] = __builtin_fma(o[P].z[q][i] * okf[q], o[P].rv[q], av[i]);
-          for (int j = 0; j < EPL; ++j) {
-            accG[i][j] = mfma16(o[P].z[q][i], y[q][j], accG[i][j]);
-            accF[i][j] = mfma16(y[q][i], y[q][j], accF[i][j]);
-            if constexpr (HAS_PREV) accE[i][j] = mfma16(o[P].pz[q][i], y[q][j], accE[i][j]);
-          }
-        }
-      }
-    }
-  };
-  for (int64_t step = S0; step < SE; step += 2 * SD) {
-    body(std::integral_constant<int, 0>{}, step);
-    if (step + SD < SE) body(std::integral_constant<int, 1>{}, step + SD);
-  }
-  if constexpr (GRAMS) {
-    for (int i = 0; i < EPL; ++i) {
-      av[i] += __shfl_xor(av[i], 16, 64);
-      av[i] += __shfl_xor(av[i], 32, 64);
-    }
-    for (int w = 0; w < NWAVE; ++w) {
-      if (wave == w) {
-        for (int i = 0; i < EPL; ++i)
-          for (int j = 0; j < EPL; ++j)
-            for (int v = 0; v < 4; ++v) {
-              const int idx = (16 * i + 4 * v + rq) * TPI + 16 * j + m;
-              const bool first = (w == 0);
-              lds[idx] = (first ? 0.0 : lds[idx]) + accG[i][j][v];
-              lds[T2 + idx] = (first ? 0.0 : lds[T2 + idx]) + accF[i][j][v];
-              lds[2 * T2 + idx] = (first ? 0.0 : lds[2 * T2 + idx]) + accE[i][j][v];
-            }
-        if (rq == 0)
-          for (int i = 0; i < EPL; ++i) {
-            const int idx = 3 * T2 + 16 * i + m;
-            lds[idx] = (w == 0 ? 0.0 : lds[idx]) + av[i];
-          }
-      }
-      __syncthreads();
-    }
-    write_partial(lds, L, a.rc);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Column-split forms for blocks of 32 and 64 stored columns.  A row group of
-// TPI/16 waves shares its rows; wave w computes the output columns
-// [16 cb, 16 cb + 16), cb = w mod (TPI/16), and the Gram columns of the same
-// block, so a lane holds one output value per row and 16 x TPI Gram
-// accumulators per Gram instead of TPI x TPI.  The waves of a row group load
-// the same full operand rows (the repeats hit the cache).  Every row group
-// writes its own partial: the partial count is the grid times kCSGroups.
-// ---------------------------------------------------------------------------
-
-template <int TPI>
-struct CsCfg {
-  static constexpr int EPL = TPI / 16;                 // column blocks = waves per row group
-  static constexpr int THREADS = cs_threads(TPI);
-  static constexpr int NWAVE = THREADS / 64;
-  static constexpr int RGRP = NWAVE / EPL;             // row groups per work-group (kCSGroups)
-  static constexpr int RPL = ECG_CS_RPL;               // row quads per lane
-  static constexpr int WROWS = 4 * RPL;
-  static constexpr int WGROWS = WROWS * RGRP;
-  static constexpr int T2 = TPI * TPI;
-  static_assert(RGRP >= 1 && kCSGroups % RGRP == 0, "row groups per work-group");
-};
-
-// v[cb] for a wave-uniform runtime cb, without indexing a register array
-template <int EPL>
-__device__ __forceinline__ double pick(const double (&v)[EPL], int cb) {
-  double r = v[0];
-  for (int e = 1; e < EPL; ++e) r = (cb == e) ? v[e] : r;
-  return r;
-}
-
 // Block update and Grams on the matrix cores (32 and 64 columns; at 16
 // columns binary32 blocks and the binary64 launches with Grams, while the
 // binary64 pure updates keep the VALU kernel above, measured faster).  A
@@ -2350,186 +1856,6 @@ void k_update_gram_mf(UGArgs<S> a) {
   }
 }
 
-template <int TPI, typename S, typename SA, bool GRAMS, bool HAS_PREV>
-__global__ __launch_bounds__(cs_threads(TPI)) __attribute__((amdgpu_waves_per_eu(ECG_CS_WPE, ECG_CS_WPE)))
-void k_spmm_cs(SpArgs<S, SA> a) {
-  using C = CsCfg<TPI>;
-  constexpr int EPL = C::EPL, RPL = C::RPL, T2 = C::T2;
-  constexpr int L = 3 * T2 + TPI;
-  // A Z rows of the current step, shared by the waves of a row group (F Gram);
-  // for binary64 blocks also Z and A Z_prev: each wave loads its own column
-  // block and reads the others from LDS (measured: 20.6 -> 17.1 ms at 256^3;
-  // no gain for binary32 blocks, whose rows are half as long)
-  constexpr int TS = GRAMS ? C::RGRP * C::WROWS * TPI : 1;
-  constexpr bool ZL = ECG_CS_ZLDS != 0 && GRAMS && sizeof(S) == 8;
-  __shared__ double yt[GRAMS ? 2 : 1][TS];
-  __shared__ double zt[ZL ? 2 : 1][ZL ? TS : 1];
-  __shared__ double pzt[ZL && HAS_PREV ? 2 : 1][ZL && HAS_PREV ? TS : 1];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m = lane & 15, rq = lane >> 4;
-  const int cb = wave % EPL, rg = wave / EPL;
-
-  d4 accG[EPL], accF[EPL], accE[EPL];
-  for (int i = 0; i < EPL; ++i) {
-    accG[i] = d4{0.0, 0.0, 0.0, 0.0};
-    accF[i] = d4{0.0, 0.0, 0.0, 0.0};
-    accE[i] = d4{0.0, 0.0, 0.0, 0.0};
-  }
-  double av = 0.0;
-  const int64_t n = a.n;
-  const int nnz_last = a.rowptr[n] - 1;
-  const Steps sp = my_steps((n + C::WGROWS - 1) / C::WGROWS);
-
-  // software pipeline as in k_spmm: row pointers two steps ahead, the first
-  // chunk of (column, value) pairs one step ahead of the gather
-  struct RowPtr {
-    int p0[RPL], p1[RPL];
-  };
-  struct Head {
-    double offb[RPL], valb[RPL];
-  };
-  auto load_rowptr = [&](int64_t step, RowPtr& rp) {
-    const int64_t row0 = step * C::WGROWS + rg * C::WROWS + rq;
-    for (int q = 0; q < RPL; ++q) {
-      const int64_t row = row0 + 4 * q;
-      const int64_t rc = row < n ? row : n - 1;
-      rp.p0[q] = ld_s(a.rowptr + rc);
-      rp.p1[q] = ld_s(a.rowptr + rc + 1);
-    }
-  };
-  auto load_chunk = [&](const RowPtr& rp, int c, Head& h) {
-    for (int q = 0; q < RPL; ++q) {
-      const int idx = rp.p0[q] + c + (m % kChunk);
-      const int idc = min(idx, nnz_last);
-      const int64_t msk = opaque((int64_t)(idx < rp.p1[q] ? -1 : 0));
-      const double okm = opaque(idx < rp.p1[q] ? 1.0 : 0.0);
-      const int64_t col = ld_s(a.colind + idc);
-      h.offb[q] = __builtin_bit_cast(double, (int64_t)(col * TPI) & msk);
-      h.valb[q] = static_cast<double>(ld_s(a.vals + idc)) * okm;
-    }
-  };
-  auto gather = [&](const Head& h, double (&y)[RPL]) {
-    static_for<kChunk>([&](auto jc) {
-      constexpr int j = decltype(jc)::value;
-      for (int q = 0; q < RPL; ++q) {
-        const int64_t off = __builtin_bit_cast(int64_t, bcast64<j>(h.offb[q]));
-        const double vj = bcast64<j>(h.valb[q]);
-        y[q] = __builtin_fma(vj, ld(a.Z + off + 16 * cb + m), y[q]);
-      }
-    });
-  };
-
-  RowPtr rp_cur, rp_nxt;
-  Head h_cur;
-  int64_t step = sp.first;
-  if (step < sp.end) {
-    load_rowptr(step, rp_cur);
-    load_chunk(rp_cur, 0, h_cur);
-    if (step + sp.stride < sp.end) load_rowptr(step + sp.stride, rp_nxt);
-  }
-  int buf = 0;
-  for (; step < sp.end; step += sp.stride) {
-    const int64_t s1 = step + sp.stride, s2 = s1 + sp.stride;
-    const bool has1 = s1 < sp.end, has2 = s2 < sp.end;
-    Head h_nxt;
-    RowPtr rp_nn;
-    if (has1) load_chunk(rp_nxt, 0, h_nxt);
-    if (has2) load_rowptr(s2, rp_nn);
-
-    const int64_t row0 = step * C::WGROWS + rg * C::WROWS + rq;
-    int64_t rowc[RPL];
-    double okf[RPL];
-    int len = 0;
-    for (int q = 0; q < RPL; ++q) {
-      const int64_t row = row0 + 4 * q;
-      rowc[q] = row < n ? row : n - 1;
-      okf[q] = opaque(row < n ? 1.0 : 0.0);
-      len = max(len, rp_cur.p1[q] - rp_cur.p0[q]);
-    }
-    double z[RPL][EPL], pz[RPL][EPL], rv[RPL];
-    if constexpr (GRAMS) {
-      for (int q = 0; q < RPL; ++q) {
-        rv[q] = ld_s(a.rvec + rowc[q]) * okf[q];
-        for (int e = 0; e < EPL; ++e) {
-          if (ZL && e > 0) break;   // own column block only (index 0 holds it)
-          const int col = ZL ? 16 * cb + m : m + 16 * e;
-          z[q][e] = ld(a.Z + rowc[q] * TPI + col) * okf[q];
-          if constexpr (HAS_PREV)
-            pz[q][e] = static_cast<double>(ld_s(a.AZprev + rowc[q] * TPI + col)) * okf[q];
-          else
-            pz[q][e] = 0.0;
-        }
-      }
-    }
-    double y[RPL];
-    for (int q = 0; q < RPL; ++q) y[q] = 0.0;
-    gather(h_cur, y);
-    for (int c = kChunk; c < len; c += kChunk) {   // rows longer than one chunk
-      Head h;
-      load_chunk(rp_cur, c, h);
-      gather(h, y);
-    }
-    for (int q = 0; q < RPL; ++q) {
-      const int64_t row = row0 + 4 * q;
-      if (row < n) st_s(a.AZ + row * TPI + 16 * cb + m, static_cast<S>(y[q]));
-    }
-    if constexpr (GRAMS) {
-      double* t = &yt[buf][rg * C::WROWS * TPI];
-      for (int q = 0; q < RPL; ++q) {
-        // the stored (rounded) value of A Z enters the Grams
-        y[q] = static_cast<double>(static_cast<S>(y[q])) * okf[q];
-        t[(rq + 4 * q) * TPI + 16 * cb + m] = y[q];
-      }
-      if constexpr (ZL) {
-        double* tz = &zt[buf][rg * C::WROWS * TPI];
-        double* tp = &pzt[HAS_PREV ? buf : 0][HAS_PREV ? rg * C::WROWS * TPI : 0];
-        for (int q = 0; q < RPL; ++q) {
-          tz[(rq + 4 * q) * TPI + 16 * cb + m] = z[q][0];
-          if constexpr (HAS_PREV) tp[(rq + 4 * q) * TPI + 16 * cb + m] = pz[q][0];
-        }
-      }
-      __syncthreads();
-      if constexpr (ZL) {
-        const double* tz = &zt[buf][rg * C::WROWS * TPI];
-        const double* tp = &pzt[HAS_PREV ? buf : 0][HAS_PREV ? rg * C::WROWS * TPI : 0];
-        for (int q = 0; q < RPL; ++q)
-          for (int e = 0; e < EPL; ++e) {
-            z[q][e] = tz[(rq + 4 * q) * TPI + 16 * e + m];
-            if constexpr (HAS_PREV) pz[q][e] = tp[(rq + 4 * q) * TPI + 16 * e + m];
-          }
-      }
-      for (int q = 0; q < RPL; ++q) {
-        av = __builtin_fma(pick<EPL>(z[q], cb), rv[q], av);
-        for (int i = 0; i < EPL; ++i) {
-          const double yi = t[(rq + 4 * q) * TPI + 16 * i + m];
-          accG[i] = mfma16(z[q][i], y[q], accG[i]);
-          accF[i] = mfma16(yi, y[q], accF[i]);
-          if constexpr (HAS_PREV) accE[i] = mfma16(pz[q][i], y[q], accE[i]);
-        }
-      }
-      buf ^= 1;   // the next step writes the other tile: one barrier per step
-    }
-    if (has1) {
-      h_cur = h_nxt;
-      rp_cur = rp_nxt;
-    }
-    if (has2) rp_nxt = rp_nn;
-  }
-  if constexpr (GRAMS) {
-    av += __shfl_xor(av, 16, 64);
-    av += __shfl_xor(av, 32, 64);
-    double* mine = a.rc.partials + ((size_t)blockIdx.x * C::RGRP + rg) * L;
-    for (int i = 0; i < EPL; ++i)
-      for (int v = 0; v < 4; ++v) {
-        const int idx = (16 * i + 4 * v + rq) * TPI + 16 * cb + m;
-        mine[idx] = accG[i][v];
-        mine[T2 + idx] = accF[i][v];
-        mine[2 * T2 + idx] = accE[i][v];
-      }
-    if (rq == 0) mine[3 * T2 + 16 * cb + m] = av;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Product kernel for 64-column blocks: A Z, with the Grams G = Z^t (A Z)
 // (A-CholQR), F = (A Z)^t (A Z), E = (A Z_prev)^t (A Z) (the next block's
@@ -2576,20 +1902,6 @@ constexpr int kP64TileN[4][5] = {{0x03, 0x07, 0x0B, 0x0F, 0x13},
 
 constexpr int p64_tile(int w, bool hp, int k) { return hp ? kP64TileE[w][k] : kP64TileN[w][k]; }
 
-// Row steps of the 64-column product.  ECG_P64_MAP 0: each XCD sweeps a
-// contiguous eighth of the rows (my_steps); 1: all work-groups sweep the rows
-// together, the work-groups of one XCD taking adjacent steps, so that the
-// +-nx*ny neighbour planes of every XCD are the same few planes (shared in
-// the last-level cache) instead of eight separate ones.
-__device__ __forceinline__ Steps p64_steps(int64_t nsteps) {
-  const int G = gridDim.x;
-  if (ECG_P64_MAP == 1 && G % 8 == 0 && G >= 64) {
-    const int xcd = blockIdx.x % 8, local = blockIdx.x / 8, per = G / 8;
-    return Steps{(int64_t)xcd * per + local, nsteps, G};
-  }
-  return my_steps(nsteps);
-}
-
 template <typename S, typename SA, bool GRAMS, bool HAS_PREV, int W>
 __device__ __forceinline__ void p64_run(const SpArgs<S, SA>& a, double* tiles, double* asum) {
   constexpr int TPI = 64, T2 = TPI * TPI, R = kP64R, LD = kP64LD, CH = kP64CH;
@@ -2599,7 +1911,7 @@ __device__ __forceinline__ void p64_run(const SpArgs<S, SA>& a, double* tiles, d
   const int m = lane & 15, rq = lane >> 4;
   const int64_t n = a.n;
   const int nnz_last = a.rowptr[n] - 1;
-  const Steps sp = p64_steps((n + R - 1) / R);
+  const Steps sp = my_steps((n + R - 1) / R);
   // lanes 8 q + j (q < 4, j < CH) hold entry j of the current chunk of row q
   const int q_l = (lane >> 3) & 3, j_l = lane & 7;
 
@@ -2788,6 +2100,249 @@ void k_spmm64(SpArgs<S, SA> a) {
       for (int w = 0; w < 4; ++w) s += asum[w * 64 + threadIdx.x];
       mine[3 * T2 + threadIdx.x] = s;
     }
+  }
+}
+
+// Producer/consumer form of the 64-column product (12 waves per work-group,
+// one work-group per CU).  Waves 0-7 (producers) gather: wave w forms rows
+// 2 w, 2 w + 1 of each 16-row step as above, with the neighbour rows of a
+// step requested two steps ahead (the (column, value) pairs three steps
+// ahead, the row pointers four; two steps of requests stay within the 63
+// vector-memory instructions a wave can have in flight), and park the
+// step's Z, A Z and A Z_prev rows in an LDS slot.  Waves 8-11 (consumers)
+// run the Gram tiles on the matrix cores, one step behind: iteration i
+// produces step i into slot i % 2 while the consumers read step i - 1 from
+// the other slot, so one barrier per iteration orders both and the matrix
+// cores do not wait for a gather.  Each SIMD holds two producer waves and
+// one consumer wave: their VALU / memory and MFMA instructions co-issue.
+#ifndef ECG_PC_R
+#define ECG_PC_R 16
+#endif
+#ifndef ECG_PC_PR
+#define ECG_PC_PR 2
+#endif
+constexpr int kPCR = ECG_PC_R;                // rows per step of the producer/consumer form
+constexpr int kP64PR = ECG_PC_PR;             // rows of a step per producer wave
+constexpr int kP64NP = kPCR / kP64PR;         // producer waves
+constexpr int kP64THREADS = 64 * (kP64NP + 4);
+
+template <typename S, typename SA, bool HAS_PREV>
+struct P64Prod {
+  static constexpr int TPI = 64, R = kPCR, LD = kP64LD, CH = kP64CH, PR = kP64PR;
+  struct RowPtr { int p0, p1; };
+  struct Head { int col; double val; };
+  struct Rows { double zg[PR][CH]; double zo[PR], po[PR], rv[PR]; };
+
+  const SpArgs<S, SA>& a;
+  int64_t n, first, stride;
+  int N, nnz_last, lane, q_l, j_l, w;
+
+  // Every load and store below is issued unconditionally (past the last
+  // step the last step is read and its values stored again), so that the
+  // compiler's count of outstanding memory operations stays exact across
+  // the pipelined loop and its waits cover only what they must.
+  __device__ int64_t step_of(int j) const { return first + (int64_t)min(j, N - 1) * stride; }
+  __device__ void load_rowptr(int j, RowPtr& rp) const {
+    const int64_t rl = step_of(j) * R + PR * w + q_l;
+    const int64_t rlc = rl < n ? rl : n - 1;
+    rp.p0 = ld_s(a.rowptr + rlc);
+    rp.p1 = ld_s(a.rowptr + rlc + 1);
+  }
+  // entries past the row's end (or past CH) read a valid entry with the
+  // value zero; rows have at most CH entries (checked by the launcher)
+  __device__ void load_head(const RowPtr& rp, Head& h) const {
+    const int idx = rp.p0 + j_l;
+    const int idc = min(idx, nnz_last);
+    h.col = ld_s(a.colind + idc);
+    h.val = static_cast<double>(ld_s(a.vals + idc)) * opaque(idx < rp.p1 && j_l < CH ? 1.0 : 0.0);
+  }
+  __device__ void load_rows(int j, const Head& h, Rows& d) const {
+    static_for<PR>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      static_for<CH>([&](auto jc) {
+        constexpr int jj = decltype(jc)::value;
+        const int cj = __builtin_amdgcn_readlane(h.col, 8 * q + jj);
+        d.zg[q][jj] = ld(a.Z + (int64_t)cj * TPI + lane);
+      });
+    });
+    for (int q = 0; q < PR; ++q) {
+      const int64_t row = step_of(j) * R + PR * w + q;
+      const int64_t rc = row < n ? row : n - 1;
+      d.zo[q] = ld(a.Z + rc * TPI + lane);
+      d.po[q] = HAS_PREV ? static_cast<double>(ld_s(a.AZprev + rc * TPI + lane)) : 0.0;
+      d.rv[q] = ld_s(a.rvec + rc);
+    }
+  }
+  __device__ static double head_val(double val, int q, int jj) {
+    const uint64_t vb = __builtin_bit_cast(uint64_t, val);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)vb, 8 * q + jj);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(vb >> 32), 8 * q + jj);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+  }
+  // A Z of step j from its gathered rows, stored; the step's tiles to LDS.
+  // Rows past n (clamped to n - 1) compute row n - 1's value again and store
+  // it there; they enter the tiles and a as zeros.  Past the last step
+  // (j >= N) the tiles are written but not read and a is not accumulated.
+  __device__ void produce(int j, const Head& h0, const Rows& d, double* tb, double& av) const {
+    const int64_t row0 = step_of(j) * R + PR * w;
+    const double live = j < N ? 1.0 : 0.0;
+    static_for<PR>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      double y = 0.0;
+      static_for<CH>([&](auto jc) {
+        constexpr int jj = decltype(jc)::value;
+        y = __builtin_fma(head_val(h0.val, q, jj), d.zg[q][jj], y);
+      });
+      const int64_t row = row0 + q;
+      const int64_t rc = row < n ? row : n - 1;
+      const double okf = row < n ? 1.0 : 0.0;
+      st_s(a.AZ + rc * TPI + lane, static_cast<S>(y));
+      const int r = PR * w + q;
+      // the stored (rounded) value of A Z enters the Grams
+      tb[r * LD + lane] = d.zo[q] * okf;
+      tb[R * LD + r * LD + lane] = static_cast<double>(static_cast<S>(y)) * okf;
+      if constexpr (HAS_PREV) tb[2 * R * LD + r * LD + lane] = d.po[q] * okf;
+      av = __builtin_fma(d.zo[q] * (okf * live), d.rv[q], av);
+    });
+  }
+};
+
+template <typename S, typename SA, bool HAS_PREV, int W>
+__device__ __forceinline__ void p64pc_consume(const double* tb, d4 (&acc)[HAS_PREV ? 9 : 5],
+                                              int lane) {
+  constexpr int R = kPCR, LD = kP64LD, NT = HAS_PREV ? 9 : 5;
+  const int m = lane & 15, rq = lane >> 4;
+  const double* X = tb;
+  const double* Y = tb + R * LD;
+  const double* P = tb + 2 * R * LD;
+  // one K-step's operands live at a time (the nine MFMAs of a step cover
+  // the next step's LDS reads)
+#pragma unroll 1
+  for (int kk = 0; kk < R / 4; ++kk) {
+    const int ro = (4 * kk + rq) * LD + m;
+    static_for<NT>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      constexpr int code = p64_tile(W, HAS_PREV, k);
+      constexpr int mat = code >> 4, ta = (code >> 2) & 3, tbk = code & 3;
+      const double* M = mat == 0 ? X : (mat == 1 ? Y : P);
+      acc[k] = mfma16(M[ro + 16 * ta], Y[ro + 16 * tbk], acc[k]);
+    });
+  }
+}
+
+template <typename S, typename SA, bool HAS_PREV, int W>
+__device__ __forceinline__ void p64pc_consumer(const SpArgs<S, SA>& a, double* tiles, int N) {
+  constexpr int T2 = 64 * 64, TPI = 64, NT = HAS_PREV ? 9 : 5;
+  constexpr int TB = 3 * kPCR * kP64LD;
+  const int lane = threadIdx.x & 63;
+  const int m = lane & 15, rq = lane >> 4;
+  d4 acc[NT];
+  for (int k = 0; k < NT; ++k) acc[k] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i <= N; i += 2) {
+    if (i >= 1) p64pc_consume<S, SA, HAS_PREV, W>(tiles + TB, acc, lane);   // step i - 1
+    __syncthreads();
+    if (i + 1 > N) break;
+    p64pc_consume<S, SA, HAS_PREV, W>(tiles, acc, lane);                    // step i
+    __syncthreads();
+  }
+  constexpr int L = 3 * T2 + TPI;
+  double* mine = a.rc.partials + (size_t)blockIdx.x * L;
+  static_for<NT>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    constexpr int code = p64_tile(W, HAS_PREV, k);
+    constexpr int mat = code >> 4, ta = (code >> 2) & 3, tbk = code & 3;
+    for (int v = 0; v < 4; ++v)
+      mine[mat * T2 + (16 * ta + 4 * v + rq) * TPI + 16 * tbk + m] = acc[k][v];
+  });
+}
+
+template <typename S, typename SA, bool HAS_PREV>
+__device__ __forceinline__ void p64pc_producer(const SpArgs<S, SA>& a, double* tiles,
+                                               double* asum, int N, const Steps& sp) {
+  constexpr int TB = 3 * kPCR * kP64LD;
+  using Pr = P64Prod<S, SA, HAS_PREV>;
+  const int lane = threadIdx.x & 63;
+  Pr pr{a, a.n, sp.first, sp.stride, N, a.rowptr[a.n] - 1, lane, (lane >> 3) % kP64PR,
+        lane & 7, (int)(threadIdx.x >> 6)};
+  double av = 0.0;
+  if (N > 0) {
+    typename Pr::RowPtr q[2], r0, r1;
+    typename Pr::Head hh[2], h_cur[2];
+    typename Pr::Rows rows[2];
+    // prologue: rows of steps 0, 1; heads of steps 0, 1 (kept for the
+    // values) and 2; row pointers of step 3
+    pr.load_rowptr(0, r0);
+    pr.load_rowptr(1, r1);
+    pr.load_rowptr(2, q[0]);
+    pr.load_head(r0, h_cur[0]);
+    pr.load_head(r1, h_cur[1]);
+    pr.load_head(q[0], hh[0]);
+    pr.load_rowptr(3, q[1]);
+    pr.load_rows(0, h_cur[0], rows[0]);
+    pr.load_rows(1, h_cur[1], rows[1]);
+    // iteration i (parity K): produce step i from rows[K] / h_cur[K]; then
+    // request head i + 3 (row pointers q[1 - K]) into hh[1 - K], row
+    // pointers i + 4 into q[K], and the rows of step i + 2 (head hh[K])
+    // into rows[K].  Issued in that order, every wait is for the oldest
+    // requests: the rows of step i + 1 stay in flight.
+    auto iter = [&](int i, auto kc) {
+      constexpr int K = decltype(kc)::value;
+      pr.produce(i, h_cur[K], rows[K], tiles + K * TB, av);
+      pr.load_head(q[1 - K], hh[1 - K]);
+      pr.load_rowptr(i + 4, q[K]);
+      h_cur[K] = hh[K];
+      pr.load_rows(i + 2, hh[K], rows[K]);
+    };
+    for (int i = 0; i <= N; i += 2) {
+      iter(i, std::integral_constant<int, 0>{});
+      __syncthreads();
+      if (i + 1 > N) break;
+      iter(i + 1, std::integral_constant<int, 1>{});
+      __syncthreads();
+    }
+  } else {
+    __syncthreads();   // the consumers' single barrier
+  }
+  asum[(threadIdx.x >> 6) * 64 + lane] = av;
+}
+
+template <typename S, typename SA, bool HAS_PREV>
+__global__ __launch_bounds__(kP64THREADS) __attribute__((amdgpu_waves_per_eu(3, 3)))
+void k_spmm64pc(SpArgs<S, SA> a) {
+  constexpr int T2 = 64 * 64;
+  __shared__ double tiles[2 * 3 * kPCR * kP64LD];
+  __shared__ double asum[kP64NP * 64];
+  const int wave = threadIdx.x >> 6;
+  // all work-groups sweep the rows together, the 1/8 of them on one XCD
+  // taking adjacent steps (G / 8 steps of 16 rows per XCD and round)
+  const int64_t nsteps = (a.n + kPCR - 1) / kPCR;
+  const int G = gridDim.x;
+  const Steps sp = (G % 8 == 0) ? Steps{(int64_t)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8,
+                                        nsteps, G}
+                                : Steps{blockIdx.x, nsteps, G};
+  const int N = sp.first < sp.end ? (int)((sp.end - sp.first + sp.stride - 1) / sp.stride) : 0;
+  switch (wave - kP64NP) {
+    case 0: p64pc_consumer<S, SA, HAS_PREV, 0>(a, tiles, N); break;
+    case 1: p64pc_consumer<S, SA, HAS_PREV, 1>(a, tiles, N); break;
+    case 2: p64pc_consumer<S, SA, HAS_PREV, 2>(a, tiles, N); break;
+    case 3: p64pc_consumer<S, SA, HAS_PREV, 3>(a, tiles, N); break;
+    default: p64pc_producer<S, SA, HAS_PREV>(a, tiles, asum, N, sp); break;
+  }
+  constexpr int L = 3 * T2 + 64;
+  double* mine = a.rc.partials + (size_t)blockIdx.x * L;
+  // tiles below the diagonal of G and F are not formed: zero (the tail
+  // mirrors F and reads only the upper triangle of G); E without a
+  // previous block is zero
+  for (int idx = threadIdx.x; idx < 3 * T2; idx += blockDim.x) {
+    const int mat = idx / T2, e = idx % T2;
+    const int br = (e / 64) / 16, bc = (e % 64) / 16;
+    if ((mat < 2 && br > bc) || (mat == 2 && !HAS_PREV)) mine[idx] = 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double s = 0.0;
+    for (int w = 0; w < kP64NP; ++w) s += asum[w * 64 + threadIdx.x];
+    mine[3 * T2 + threadIdx.x] = s;
   }
 }
 
@@ -3082,6 +2637,24 @@ __global__ __launch_bounds__(kThreads) void k_final(const double* __restrict__ g
 // Launchers
 // ---------------------------------------------------------------------------
 
+int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+int spmm_partials(int tpi, int grid, int max_row) {
+  if (uses_cs(tpi) && max_row <= kP64CH) return std::max(1, std::min(grid * kCSGroups, device_cus()));
+  return gram_partials(tpi, grid);
+}
+
 static int simple_grid(int64_t work) {
   int64_t g = (work + kThreads - 1) / kThreads;
   if (g > 4096) g = 4096;
@@ -3196,109 +2769,46 @@ hipError_t launch_update_gram(int nu, int ng, bool ident0, bool write_out, int t
   return hipErrorInvalidValue;
 }
 
+// The product kernel for a block width and storage type: 16 columns
+// k_spmm_wide (binary64) / k_spmm_widef (binary32), 32 columns k_spmm_w32 /
+// k_spmm_w32f, 64 columns the producer/consumer k_spmm64pc (rows of at most
+// kP64CH entries) or k_spmm64 (any rows, and the product without Grams).
 template <int TPI, typename S, typename SA>
 hipError_t launch_spmm(bool grams, bool has_prev, int tail, const SpArgs<S, SA>& a, int grid,
                        hipStream_t st) {
-  if constexpr (uses_cs(TPI) && ECG_P64) {
-    // kCSGroups work-groups (one Gram partial each) per unit of `grid`
-    const dim3 blk(kThreads), g(grid * kCSGroups);
-    if (grams && tail != TAIL_SPMM) return hipErrorInvalidValue;
-    if (!grams)
-      hipLaunchKernelGGL((k_spmm64<S, SA, false, false>), g, blk, 0, st, a);
-    else if (has_prev)
-      hipLaunchKernelGGL((k_spmm64<S, SA, true, true>), g, blk, 0, st, a);
-    else
-      hipLaunchKernelGGL((k_spmm64<S, SA, true, false>), g, blk, 0, st, a);
-    return hipGetLastError();
-  }
-  if constexpr (uses_cs(TPI)) {
-    // kCSGroups row groups (one Gram partial each) per unit of `grid`
-    const dim3 blk(cs_threads(TPI)), g(grid * (kCSGroups / CsCfg<TPI>::RGRP));
-    if (grams && tail != TAIL_SPMM) return hipErrorInvalidValue;
-    if (!grams)
-      hipLaunchKernelGGL((k_spmm_cs<TPI, S, SA, false, false>), g, blk, 0, st, a);
-    else if (has_prev)
-      hipLaunchKernelGGL((k_spmm_cs<TPI, S, SA, true, true>), g, blk, 0, st, a);
-    else
-      hipLaunchKernelGGL((k_spmm_cs<TPI, S, SA, true, false>), g, blk, 0, st, a);
-    return hipGetLastError();
-  }
-  if constexpr (ECG_SP_WIDE != 0 && TPI == 16 && std::is_same<S, double>::value &&
-                std::is_same<SA, double>::value) {
-    if (grams && tail != TAIL_SPMM) return hipErrorInvalidValue;
-    if (!grams)
-      hipLaunchKernelGGL((k_spmm_wide<false, false>), dim3(grid), dim3(kThreads), 0, st, a);
-    else if (has_prev)
-      hipLaunchKernelGGL((k_spmm_wide<true, true>), dim3(grid), dim3(kThreads), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_spmm_wide<true, false>), dim3(grid), dim3(kThreads), 0, st, a);
-    return hipGetLastError();
-  }
-  if constexpr (ECG_SP_WIDE != 0 && TPI == 16 && std::is_same<S, float>::value &&
-                std::is_same<SA, float>::value) {
-    if (grams && tail != TAIL_SPMM) return hipErrorInvalidValue;
-    if (!grams)
-      hipLaunchKernelGGL((k_spmm_widef<false, false>), dim3(grid), dim3(kThreads), 0, st, a);
-    else if (has_prev)
-      hipLaunchKernelGGL((k_spmm_widef<true, true>), dim3(grid), dim3(kThreads), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_spmm_widef<true, false>), dim3(grid), dim3(kThreads), 0, st, a);
-    return hipGetLastError();
-  }
-  if constexpr (ECG_SPW32 != 0 && TPI == 32 && std::is_same<S, double>::value &&
-                std::is_same<SA, double>::value) {
+  static_assert(std::is_same<S, SA>::value, "block and matrix values share the storage type");
+  if (grams && tail != TAIL_SPMM) return hipErrorInvalidValue;
+  constexpr bool F64 = std::is_same<S, double>::value;
+#define ECG_SP3(K)                                                                         \
+  do {                                                                                     \
+    if (!grams) hipLaunchKernelGGL((K<false, false>), dim3(grid), dim3(kThreads), 0, st, a); \
+    else if (has_prev)                                                                     \
+      hipLaunchKernelGGL((K<true, true>), dim3(grid), dim3(kThreads), 0, st, a);           \
+    else hipLaunchKernelGGL((K<true, false>), dim3(grid), dim3(kThreads), 0, st, a);       \
+  } while (0)
+  if constexpr (TPI == 16 && F64) ECG_SP3(k_spmm_wide);
+  else if constexpr (TPI == 16) ECG_SP3(k_spmm_widef);
+  else if constexpr (TPI == 32 && F64) ECG_SP3(k_spmm_w32);
+  else if constexpr (TPI == 32) ECG_SP3(k_spmm_w32f);
+  else {
+    // kCSGroups work-groups (one Gram partial each) per unit of `grid`, or
+    // spmm_partials(TPI, grid, max_row) work-groups of the producer/consumer form
     if (!grams) {
-      hipLaunchKernelGGL((k_spmm_w32<false, false>), dim3(grid), dim3(kThreads), 0, st, a);
-      return hipGetLastError();
-    }
-    if (tail == TAIL_SPMM) {
-      if (has_prev)
-        hipLaunchKernelGGL((k_spmm_w32<true, true>), dim3(grid), dim3(kThreads), 0, st, a);
-      else
-        hipLaunchKernelGGL((k_spmm_w32<true, false>), dim3(grid), dim3(kThreads), 0, st, a);
-      return hipGetLastError();
-    }
-  }
-  if constexpr (ECG_SPW32 != 0 && TPI == 32 && std::is_same<S, float>::value &&
-                std::is_same<SA, float>::value) {
-    if (!grams) {
-      hipLaunchKernelGGL((k_spmm_w32f<false, false>), dim3(grid), dim3(kThreads), 0, st, a);
-      return hipGetLastError();
-    }
-    if (tail == TAIL_SPMM) {
-      if (has_prev)
-        hipLaunchKernelGGL((k_spmm_w32f<true, true>), dim3(grid), dim3(kThreads), 0, st, a);
-      else
-        hipLaunchKernelGGL((k_spmm_w32f<true, false>), dim3(grid), dim3(kThreads), 0, st, a);
-      return hipGetLastError();
+      hipLaunchKernelGGL((k_spmm64<S, SA, false, false>), dim3(grid * kCSGroups), dim3(kThreads),
+                         0, st, a);
+    } else if (a.max_row <= kP64CH) {
+      const dim3 g(spmm_partials(TPI, grid, a.max_row)), blk(kP64THREADS);
+      if (has_prev) hipLaunchKernelGGL((k_spmm64pc<S, SA, true>), g, blk, 0, st, a);
+      else hipLaunchKernelGGL((k_spmm64pc<S, SA, false>), g, blk, 0, st, a);
+    } else if (has_prev) {
+      hipLaunchKernelGGL((k_spmm64<S, SA, true, true>), dim3(grid * kCSGroups), dim3(kThreads),
+                         0, st, a);
+    } else {
+      hipLaunchKernelGGL((k_spmm64<S, SA, true, false>), dim3(grid * kCSGroups), dim3(kThreads),
+                         0, st, a);
     }
   }
-  if constexpr (TPI == 16 && (ECG_SP_DEEP == 2 || (ECG_SP_DEEP == 1 && sizeof(S) == 4))) {
-    if (grams && tail != TAIL_SPMM) return hipErrorInvalidValue;
-    if (!grams)
-      hipLaunchKernelGGL((k_spmm_deep<TPI, S, SA, false, false>), dim3(grid), dim3(kThreads), 0, st, a);
-    else if (has_prev)
-      hipLaunchKernelGGL((k_spmm_deep<TPI, S, SA, true, true>), dim3(grid), dim3(kThreads), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_spmm_deep<TPI, S, SA, true, false>), dim3(grid), dim3(kThreads), 0, st, a);
-    return hipGetLastError();
-  }
-  const bool off32 = ECG_SP_OFF32 != 0 && (uint64_t)a.n * TPI * sizeof(S) < (1ull << 32);
-#define ECG_SPL(G, H, T)                                                                    \
-  if (off32)                                                                                \
-    hipLaunchKernelGGL((k_spmm<TPI, S, SA, G, H, T, true>), dim3(grid), dim3(kThreads), 0, st, a); \
-  else                                                                                      \
-    hipLaunchKernelGGL((k_spmm<TPI, S, SA, G, H, T, false>), dim3(grid), dim3(kThreads), 0, st, a);
-  if (!grams) {
-    ECG_SPL(false, false, TAIL_NONE)
-  } else if (tail != TAIL_SPMM) {
-    return hipErrorInvalidValue;
-  } else if (has_prev) {
-    ECG_SPL(true, true, TAIL_SPMM)
-  } else {
-    ECG_SPL(true, false, TAIL_SPMM)
-  }
-#undef ECG_SPL
+#undef ECG_SP3
   return hipGetLastError();
 }
 

@@ -64,6 +64,7 @@ struct Timed {
 struct ecg_ctx {
   int64_t n = 0, nnz = 0;
   int t = 0, s = 0, tpi = 16;
+  int max_row = 0;            // most entries in a row
   ecg_opts o{};
   hipStream_t st = nullptr;
   int dev = 0;
@@ -430,6 +431,7 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   ecg_ctx* c = new ecg_ctx();
   c->n = n;
   c->nnz = nnz;
+  for (int64_t i = 0; i < n; ++i) c->max_row = std::max(c->max_row, (int)(rp[i + 1] - rp[i]));
   c->t = t;
   c->s = s;
   c->tpi = pick_tpi(t);
@@ -888,6 +890,7 @@ struct Engine {
     sa.AZprev = m >= 2 ? AU(p1) : nullptr;
     sa.rvec = c->r;
     sa.n = c->n;
+    sa.max_row = c->max_row;
     sa.rc = c->rc();
     sa.tail = tail0(m);
     sa.tail.rinv_cur = rinv(slot);
@@ -903,7 +906,8 @@ struct Engine {
                   2.0 * c->n * c->t);
     HIP_TRY((launch_spmm<TPI, S, SA>(true, m >= 2, TAIL_SPMM, sa, c->grid, c->st)));
     c->tstop(tm);
-    return reduce(gram_partials(TPI, c->grid), 3 * TPI * TPI + TPI, TAIL_SPMM, 0, sa.tail);
+    return reduce(spmm_partials(TPI, c->grid, c->max_row), 3 * TPI * TPI + TPI, TAIL_SPMM, 0,
+                  sa.tail);
   }
 
   // x2 = x_in + sum U beta, r2 = r_in - sum AU beta over the given blocks, and ||r2||
@@ -1240,6 +1244,7 @@ int spmm_op(ecg_ctx* c, double* Xp, double* Yp) {
   sa.Z = Xp;
   sa.AZ = Yp;
   sa.n = c->n;
+  sa.max_row = c->max_row;
   sa.rc = c->rc();
   const int g = (int)std::min<int64_t>((c->n + rows_per_wg(TPI) - 1) / rows_per_wg(TPI), 1024);
   HIP_TRY((launch_spmm<TPI, double, double>(false, false, TAIL_NONE, sa, g, c->st)));

@@ -237,3 +237,25 @@ def test_custom_grid_matches_default(E, m, t, s, parts, grid):
     assert np.linalg.norm(p.b - A @ x.cpu().numpy()) / np.linalg.norm(p.b) <= 1e-8
     ref.close()
     sol.close()
+
+
+def test_long_rows_64_columns(E):
+    # rows of 13 entries (the square of the 5-point Laplacian, SPD): at 64
+    # columns the general product kernel runs (the producer/consumer form
+    # takes rows of at most 7 entries); parity with the oracle on every
+    # iterate
+    p = P.poisson2d(24, t=64, parts=(8, 8, 1))
+    L = p.scipy()
+    A = (L @ L).tocsr()
+    A.sort_indices()
+    assert np.diff(A.indptr).max() == 13
+    b = A @ p.xstar
+    dom = O.partition_grid(p.shape, (8, 8, 1))
+    sol = E.Solver(A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data, dom, 64, 2)
+    ref = O.sstep_srecg(A, dom, 64, 2, b, tol=1e-8, maxit=100, record=True)
+    x, info = sol.solve(b, tol=1e-8, maxit=100)
+    assert info.status == E.OK and info.iters == ref.iters
+    assert _rel(x.cpu().numpy(), ref.x) <= 1e-8
+    x1, _ = sol.solve(b, tol=1e-8, maxit=1)
+    assert _rel(x1.cpu().numpy(), ref.extra["xs"][1]) <= 1e-10
+    sol.close()
