@@ -37,6 +37,7 @@ __all__ = [
     "csr", "partition_grid", "domain_order", "split_T", "chol_upper", "cgs2_a", "a_cholqr",
     "pre_cholqr", "cg", "srecg", "sstep_srecg", "SolveResult", "basis_matrix", "true_residual",
     "dense_cholesky_solve", "sddmm", "dense_gradient", "Breakdown",
+    "ic0", "block_jacobi_ic0", "apply_llt_inverse", "pcg",
 ]
 
 OK, MAXIT, BREAKDOWN, STAGNATED = 0, 1, 2, 3
@@ -345,7 +346,7 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
                 orth="acholqr", aimage="stored", basis_dtype=np.float64,
                 inner_tol=0.0, max_restarts=20, q_cap_blocks=0,
                 record=False, stop_after_blocks: Optional[int] = None,
-                trace: Optional[list] = None) -> SolveResult:
+                trace: Optional[list] = None, precond=None) -> SolveResult:
     """s-step SRE-CG (variant='srecg') / s-step SRE-CG2 ('srecg2') / s-step
     MSDO-CG ('msdo', Section 3.2, algorithm "s-step MSDO-CG").
 
@@ -379,6 +380,16 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
       * SRE-CG2 and MSDO-CG keep all blocks since the last restart; when
         q_cap_blocks > 0 and another s blocks would exceed it, the solve
         restarts from x.
+
+    `precond` (optional) applies M^{-1} of a preconditioner M = L L^t to an
+    n x t float64 block: the split preconditioned s-step methods of Section 5
+    ("Split preconditioned s-step SRE-CG", "... SRE-CG2", "... MSDO-CG"),
+    which A-orthonormalize V = L^{-t} V-hat instead of L^{-1} A L^{-t}-
+    orthonormalizing V-hat: the first block after a (re)start is
+    M^{-1} T(r) (for a block-diagonal M whose blocks lie inside the
+    domains, L^{-t} T(L^{-1} r) = M^{-1} T(r)), every later one
+    M^{-1} A W_{j-1}; alpha, x and r are updated with V and A V exactly as
+    without a preconditioner.
 
     `trace` (a list, optional) receives one dict per block (the CGS2 output
     Z, A Z, the Gram G, R, W and A W) and one per true-residual check (x
@@ -431,12 +442,17 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
             try:
                 for i in range(s):
                     if fresh_start or (variant == "msdo" and i == 0):
-                        Z = _store(split_T(r, dom, t), dtype)
+                        Z = split_T(r, dom, t)
                         fresh_start = False
                     elif aimage == "stored":
                         Z = blocks.last()[1].copy()
                     else:
                         Z = _spmm(Ab, blocks.last()[0], dtype)
+                    if precond is not None:
+                        # split preconditioning (Section 5): W = M^{-1} T(r)
+                        # for a first block, W = M^{-1} A W_{j-1} after it
+                        Z = precond(_f64(Z))
+                    Z = _store(Z, dtype)
                     Z = cgs2_a(Z, *blocks.all(), dtype)
                     if trace is None:
                         W, AW, _ = orthonormalize(Ab, Z, dtype)
@@ -497,6 +513,121 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
     if record:
         res.extra.update(xs=xs, rs=rs, V=Vs, alpha=alphas)
     return res
+
+
+# ---------------------------------------------------------------------------
+# Block Jacobi preconditioner with incomplete Cholesky blocks (Section 5,
+# convergence experiments) and preconditioned CG
+# ---------------------------------------------------------------------------
+
+def ic0(A: sp.csr_matrix) -> sp.csr_matrix:
+    """Incomplete Cholesky with zero fill-in: the lower triangular L with
+    the sparsity pattern of the lower triangle of A such that (L L^t)_ij =
+    A_ij for every (i, j) in that pattern, computed row by row:
+      L_ij = (A_ij - sum_{k < j} L_ik L_jk) / L_jj   for j < i in the pattern,
+      L_ii = sqrt(A_ii - sum_{k < i} L_ik^2),
+    the sums running over the pattern.  Raises Breakdown if a pivot is <= 0
+    or not finite.  Pure Python: small matrices only."""
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    n = A.shape[0]
+    rows: List[dict] = []
+    for i in range(n):
+        lo, hi = A.indptr[i], A.indptr[i + 1]
+        row = {}
+        aii = 0.0
+        for p in range(lo, hi):
+            j = int(A.indices[p])
+            if j > i:
+                break
+            if j == i:
+                aii = float(A.data[p])
+                break
+            rj = rows[j]
+            acc = float(A.data[p])
+            for k, v in row.items():
+                if k < j and k in rj:
+                    acc -= v * rj[k]
+            row[j] = acc / rj[j]
+        d = aii - sum(v * v for v in row.values())
+        if not np.isfinite(d) or d <= 0.0:
+            raise Breakdown(f"IC(0) pivot {i}: {d}")
+        row[i] = math.sqrt(d)
+        rows.append(row)
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    cols, vals = [], []
+    for i, row in enumerate(rows):
+        ks = sorted(row)
+        cols += ks
+        vals += [row[k] for k in ks]
+        indptr[i + 1] = len(cols)
+    return sp.csr_matrix((np.array(vals), np.array(cols, dtype=np.int64), indptr), shape=(n, n))
+
+
+def block_jacobi_ic0(A: sp.csr_matrix, blocks: np.ndarray) -> sp.csr_matrix:
+    """L of the block Jacobi preconditioner M = L L^t whose diagonal blocks
+    A(B_i, B_i) (rows with equal blocks[]) are factorised by IC(0)
+    (Section 5: 64 blocks, incomplete Cholesky with zero fill-in).  Entries
+    of A between different blocks are dropped first, so L is block
+    diagonal, in the original row numbering."""
+    A = sp.coo_matrix(A)
+    blocks = np.asarray(blocks)
+    keep = blocks[A.row] == blocks[A.col]
+    Abd = sp.csr_matrix((A.data[keep], (A.row[keep], A.col[keep])), shape=A.shape)
+    return ic0(Abd)
+
+
+def apply_llt_inverse(L: sp.csr_matrix):
+    """The map Z -> M^{-1} Z = L^{-t} (L^{-1} Z) for M = L L^t (two sparse
+    triangular solves, the library routine as a step)."""
+    from scipy.sparse.linalg import spsolve_triangular
+    Lc = sp.csr_matrix(L)
+    Ut = sp.csr_matrix(L.T)
+
+    def minv(Z):
+        Z = np.asarray(Z, dtype=np.float64)
+        Y = spsolve_triangular(Lc, Z, lower=True)
+        return spsolve_triangular(Ut, Y, lower=False)
+    return minv
+
+
+def pcg(A: sp.csr_matrix, b: np.ndarray, minv, x0=None, tol=1e-8, maxit=100000,
+        record=False) -> SolveResult:
+    """Preconditioned CG (the paper's preconditioned CG algorithm in
+    Section 6, M = L L^t): z = M^{-1} r, p_1 = z_0, alpha = r^t z / p^t A p,
+    beta = r_new^t z_new / r^t z, stopping on ||r_k|| <= tol ||r_0||.
+    `minv` maps a vector (or n x 1 block) r to M^{-1} r."""
+    def mv(v):
+        return np.asarray(minv(v.reshape(-1, 1)), dtype=np.float64).reshape(-1)
+    x = np.zeros_like(b) if x0 is None else x0.astype(np.float64).copy()
+    r = b - A @ x
+    rho0 = float(np.linalg.norm(r))
+    hist = [rho0]
+    xs = [x.copy()] if record else None
+    if rho0 == 0.0:
+        return SolveResult(x, 0, hist, OK, extra={"xs": xs})
+    z = mv(r)
+    p = z.copy()
+    rz = float(r @ z)
+    k = 0
+    rho = rho0
+    while rho > tol * rho0 and k < maxit:
+        Ap = A @ p
+        alpha = rz / float(p @ Ap)
+        x = x + alpha * p
+        r = r - alpha * Ap
+        z = mv(r)
+        rz_new = float(r @ z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+        rho = float(np.linalg.norm(r))
+        k += 1
+        hist.append(rho)
+        if record:
+            xs.append(x.copy())
+    status = OK if rho <= tol * rho0 else MAXIT
+    tr = float(np.linalg.norm(b - A @ x)) / rho0
+    return SolveResult(x, k, hist, status, true_relres=tr, extra={"xs": xs})
 
 
 # ---------------------------------------------------------------------------

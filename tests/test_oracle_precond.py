@@ -1,0 +1,150 @@
+"""Pins of the oracle's split preconditioned s-step SRE-CG (Section 5) and
+its block Jacobi IC(0) preconditioner, against closed forms, library
+factorisations, the exact-preconditioner case, preconditioned CG and the
+paper's Poisson2D counts.  No GPU."""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+import oracle.ecg_oracle as E
+import problems as P
+from tests import pinlib
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _table():
+    out = {}
+    with open(os.path.join(GOLDEN, "poisson2d_precond_iterations.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                parts = line.split()
+                out[(parts[0], int(parts[1]))] = [int(v) for v in parts[2:]]
+    return out
+
+
+@pytest.fixture(scope="module")
+def poisson():
+    p = P.poisson2d(100, rhs="unit", tol=1e-6)
+    A = p.scipy()
+    L = O.block_jacobi_ic0(A, O.partition_grid(p.shape, (8, 8, 1)))
+    return p, A, L, O.apply_llt_inverse(L)
+
+
+def test_ic0_of_tridiagonal_is_cholesky():
+    # no fill-in in a tridiagonal matrix: IC(0) is the exact factor
+    n = 50
+    A = sp.diags([-1.0, 2.5, -1.0], [-1, 0, 1], shape=(n, n), format="csr")
+    L = O.ic0(A).toarray()
+    assert np.allclose(L, np.linalg.cholesky(A.toarray()), rtol=0, atol=1e-14)
+
+
+def test_ic0_matches_on_pattern_only():
+    p = P.poisson2d(12, t=1, parts=(1, 1, 1))
+    A = p.scipy()
+    L = O.ic0(A)
+    assert (sp.triu(L, 1).nnz == 0) and np.array_equal(
+        sp.tril(A).tocsr().indices, L.tocsr().indices)
+    LL = (L @ L.T).toarray()
+    Ad = A.toarray()
+    pat = Ad != 0
+    assert np.abs(LL - Ad)[pat].max() <= 1e-13 * np.abs(Ad).max()
+    assert np.abs(LL - Ad)[~pat].max() > 1e-3          # the dropped fill-in
+
+
+def test_block_jacobi_is_block_diagonal(poisson):
+    p, A, L, _ = poisson
+    blk = O.partition_grid(p.shape, (8, 8, 1))
+    Lc = L.tocoo()
+    assert (blk[Lc.row] == blk[Lc.col]).all()
+    # one block on its own equals IC(0) of that diagonal block
+    rows = np.nonzero(blk == 9)[0]
+    Lb = O.ic0(A[rows][:, rows]).toarray()
+    assert np.abs(L[rows][:, rows].toarray() - Lb).max() <= 1e-15
+
+
+def test_exact_preconditioner_converges_in_one_iteration():
+    # M = A: W_1 = A^{-1} T(r_0) spans A^{-1} r_0, so x_1 = x*
+    p = P.loguniform2d(20, t=4, parts=(2, 2, 1))
+    A = p.scipy()
+    Ad = A.toarray()
+    dom = O.partition_grid(p.shape, p.parts)
+    r = O.sstep_srecg(A, dom, 4, 2, p.b, tol=1e-10,
+                      precond=lambda Z: O.dense_cholesky_solve(Ad, Z))
+    assert r.status == O.OK and r.iters == 1
+    assert np.linalg.norm(r.x - p.xstar) <= 1e-9 * np.linalg.norm(p.xstar)
+
+
+def test_t1_s1_is_preconditioned_cg(poisson):
+    # t = s = 1: one vector per iteration, M^{-1}-preconditioned CG
+    p, A, L, M = poisson
+    dom = np.zeros(p.n, dtype=np.int32)
+    ref = O.pcg(A, p.b, M, tol=1e-8, record=True)
+    r = O.sstep_srecg(A, dom, 1, 1, p.b, tol=1e-8, precond=M, record=True)
+    assert abs(r.iters - ref.iters) <= 2
+    for k in range(1, min(r.iters, ref.iters) + 1):
+        if ref.hist[k] <= 1e-6 * ref.hist[0]:
+            break
+        xr, xc = r.extra["xs"][k], ref.extra["xs"][k]
+        assert np.linalg.norm(xr - xc) <= 1e-8 * np.linalg.norm(xc), k
+    # and M = I is plain CG
+    r1 = O.pcg(A, p.b, lambda Z: Z, tol=1e-8)
+    assert r1.iters == O.cg(A, p.b, tol=1e-8).iters
+
+
+def test_preconditioned_poisson2d_counts_in_band(poisson):
+    # the paper's Metis domains vs our boxes: a +-10% band (+-2 at small counts)
+    p, A, L, M = poisson
+    tab = _table()
+    got_pcg = O.pcg(A, p.b, M, tol=1e-6).iters
+    assert abs(got_pcg - tab[("pcg", 1)][0]) <= 0.12 * tab[("pcg", 1)][0]
+    for t, parts in ((16, (4, 4, 1)), (32, (4, 8, 1)), (64, (8, 8, 1))):
+        dom = O.partition_grid(p.shape, parts)
+        for si, s in enumerate((1, 2, 4, 8)):
+            want = tab[("psre-cg", t)][si]
+            got = O.sstep_srecg(A, dom, t, s, p.b, tol=1e-6, precond=M).iters
+            assert abs(got - want) <= max(2, 0.10 * want), (t, s, got, want)
+
+
+def test_preconditioned_basis_invariants(poisson):
+    # eqs (1)-(3) hold for V = L^{-t} V-hat: A-orthonormal basis,
+    # Petrov-Galerkin residuals, and the A-norm error drop
+    p, A, L, M = poisson
+    dom = O.partition_grid(p.shape, (2, 4, 1))
+    r = O.sstep_srecg(A, dom, 8, 2, p.b, tol=1e-8, maxit=10, precond=M, record=True)
+    assert pinlib.orthonormality_violation(r, A) <= 1e-10
+    assert pinlib.petrov_galerkin_violation(r) <= 1e-10
+    assert pinlib.error_drop_violation(r, A, p.xstar) <= 1e-8
+
+
+def test_planted_half_preconditioner_is_caught(poisson, monkeypatch):
+    # applying only L^{-1} (not L^{-t} L^{-1}): not the split preconditioned
+    # method; the preconditioned-CG identity fails
+    from scipy.sparse.linalg import spsolve_triangular
+    p, A, L, M = poisson
+    Lc = sp.csr_matrix(L)
+    half = lambda Z: spsolve_triangular(Lc, np.asarray(Z, float), lower=True)  # noqa: E731
+    dom = np.zeros(p.n, dtype=np.int32)
+    ref = O.pcg(A, p.b, M, tol=1e-8)
+    bad = O.sstep_srecg(A, dom, 1, 1, p.b, tol=1e-8, maxit=400, precond=half)
+    assert abs(bad.iters - ref.iters) > 2
+
+
+def test_planted_unpreconditioned_first_block_is_caught(poisson):
+    # preconditioning only the later blocks (T(r) taken raw): the basis no
+    # longer spans the preconditioned enlarged Krylov subspace; at t = 64 the
+    # count leaves Table 6's band
+    p, A, L, M = poisson
+    dom = O.partition_grid(p.shape, (8, 8, 1))
+    calls = {"n": 0}
+
+    def skip_first(Z):
+        calls["n"] += 1
+        return Z if calls["n"] == 1 else M(Z)
+    got = O.sstep_srecg(A, dom, 64, 2, p.b, tol=1e-6, maxit=60, precond=skip_first).iters
+    want = _table()[("psre-cg", 64)][1]
+    assert abs(got - want) > max(2, 0.10 * want)
