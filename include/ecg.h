@@ -60,6 +60,8 @@ enum ecg_variant   { ECG_SRECG = 0,   /* s-step SRE-CG: each block against the
                                          SRE-CG2, but the first block of every
                                          iteration is T(r_{k-1}) */ };
 enum ecg_orth      { ECG_ACHOLQR = 0, ECG_PRECHOLQR = 1 };
+enum ecg_precond   { ECG_PREC_NONE = 0,   /* no preconditioner */
+                     ECG_PREC_BJ_IC0 = 1  /* block Jacobi, IC(0) blocks (Section 5) */ };
 enum ecg_precision { ECG_FP64 = 0,    /* everything in binary64 */
                      ECG_MIXED = 1    /* binary32 basis blocks and matrix values
                                          for the basis product; Gram matrices,
@@ -130,6 +132,7 @@ enum ecg_kclass {
   ECG_K_UPDATE,      /* stand-alone block update (SRE-CG2, Pre-CholQR) */
   ECG_K_SMALL,       /* sums of work-group partials and the t x t algebra
                         (Cholesky, R^{-1}, coefficient matrices) */
+  ECG_K_PRECOND,     /* M^{-1} of the preconditioner (both triangular solves) */
   ECG_K_COUNT
 };
 
@@ -249,6 +252,27 @@ int ecg_tsplit(ecg_ctx* c, const double* r, double* Z);
  * iteration), ECG_EDEVICE.
  */
 int ecg_get_basis(ecg_ctx* c, double* V, double* AV);
+
+/*
+ * Split preconditioning of the s-step methods (Section 5: the system
+ * L^{-1} A L^{-t} (L^t x) = L^{-1} b with M = L L^t, solved by
+ * A-orthonormalizing V = L^{-t} V-hat; the first block after a restart is
+ * M^{-1} T(r), every later one starts from M^{-1} A W_{j-1}).
+ * kind = ECG_PREC_BJ_IC0: the block Jacobi preconditioner whose diagonal
+ * blocks A(B, B), B = {i : blocks[i] = b}, are factorised by incomplete
+ * Cholesky with zero fill-in (the paper's experiments use 64 blocks, each of
+ * the t domains a union of blocks); blocks (n int32 values >= 0, host or
+ * device array as the context's other arrays, caller's row order) must
+ * place every block inside one domain.  The factorisation runs on the host;
+ * the two triangular solves of every application run on the device, level
+ * by level.  kind = ECG_PREC_NONE (blocks ignored) removes it.  Applies to
+ * every later ecg_solve on the context (all variants and both precision
+ * forms).  Errors: ECG_EINVAL (bad kind; NULL blocks; a negative value; a
+ * block spanning two domains; an IC(0) pivot <= 0: the matrix is then not
+ * suitable for IC(0)), ECG_ENOMEM, ECG_EDEVICE; on error no preconditioner
+ * is set.
+ */
+int ecg_set_preconditioner(ecg_ctx* c, int32_t kind, const int32_t* blocks);
 
 /*
  * The solver's row order: order[i] (n int32 values, host or device array as

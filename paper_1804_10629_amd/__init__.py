@@ -34,7 +34,8 @@ SRECG, SRECG2, MSDO = 0, 1, 2
 ACHOLQR, PRECHOLQR = 0, 1
 FP64, MIXED = 0, 1
 KCLASSES = ["resid", "tsplit", "cgs_gram", "cgs_update", "spmm", "xr_update", "gram",
-            "update", "small"]
+            "update", "small", "precond"]
+PREC_NONE, PREC_BJ_IC0 = 0, 1
 
 
 class EcgError(RuntimeError):
@@ -67,8 +68,8 @@ class _Result(ctypes.Structure):
 
 class _Stats(ctypes.Structure):
     _fields_ = [
-        ("launches", ctypes.c_int64 * 9), ("ms", ctypes.c_double * 9),
-        ("bytes", ctypes.c_double * 9), ("flops", ctypes.c_double * 9),
+        ("launches", ctypes.c_int64 * 10), ("ms", ctypes.c_double * 10),
+        ("bytes", ctypes.c_double * 10), ("flops", ctypes.c_double * 10),
     ]
 
 
@@ -93,6 +94,7 @@ _SIGS = {
     "ecg_get_basis": (ctypes.c_int, [_P, _P, _P]),
     "ecg_last_stats": (ctypes.c_int, [_P, ctypes.POINTER(_Stats)]),
     "ecg_domain_order": (ctypes.c_int, [_P, _P]),
+    "ecg_set_preconditioner": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "ecg_destroy": (None, [_P]),
 }
 
@@ -206,7 +208,8 @@ class Solver:
                  variant: int = SRECG, orth: int = ACHOLQR, precision: int = FP64,
                  inner_tol: float = 1e-4, max_restarts: int = 20, q_cap_blocks: int = 0,
                  ws_cap_bytes: int = 0, collect_stats: bool = False, grid: int = 0,
-                 progress_every: int = 0, permute_domains: bool = True):
+                 progress_every: int = 0, permute_domains: bool = True,
+                 precond_blocks=None):
         torch = _torch()
         self._ctx = _P()
         o = _Opts()
@@ -228,6 +231,16 @@ class Solver:
         self.t, self.s = int(t), int(s)
         _check(lib.ecg_setup(ctypes.byref(self._ctx), self.n, rp.data_ptr(), ci.data_ptr(),
                              va.data_ptr(), pd.data_ptr(), self.t, self.s, ctypes.byref(o)))
+        if precond_blocks is not None:
+            self.set_preconditioner(PREC_BJ_IC0, precond_blocks)
+
+    def set_preconditioner(self, kind: int, blocks=None):
+        """Block Jacobi IC(0) preconditioner with blocks[i] the block of row i
+        (kind PREC_BJ_IC0), or none (PREC_NONE)."""
+        torch = _torch()
+        bd = _dev_tensor(blocks, torch.int32) if blocks is not None else None
+        _check(lib.ecg_set_preconditioner(self._ctx, int(kind),
+                                          bd.data_ptr() if bd is not None else None))
 
     def close(self):
         if getattr(self, "_ctx", None) and self._ctx.value:

@@ -143,6 +143,12 @@ template <int TPI, typename S>
 hipError_t launch_tsplit(const double* r, const int32_t* dom, S* Z, int64_t n, int grid,
                          hipStream_t st);
 
+// One level (count rows) of the level-scheduled triangular solve, in place
+// on the n x TPI block X (k_trsv_level).
+template <int TPI, typename S>
+hipError_t launch_trsv_level(const int32_t* lrows, int count, const int32_t* rp, const int32_t* ci,
+                             const double* v, const double* dinv, S* X, hipStream_t st);
+
 template <int TPI, typename S>
 hipError_t launch_update_gram(int nu, int ng, bool ident0, bool write_out, int tail,
                               const UGArgs<S>& a, int grid, hipStream_t st);

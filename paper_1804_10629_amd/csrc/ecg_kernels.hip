@@ -765,6 +765,32 @@ __global__ __launch_bounds__(kThreads) void k_tsplit(const double* __restrict__ 
   }
 }
 
+// One level of a sparse triangular solve with an n x TPI block, in place:
+// X[i] = (X[i] - sum_j T[i][j] X[j]) * dinv[i] for the rows i of the level
+// (T strictly lower for L y = x, strictly upper for L^t z = y; every j is
+// in an earlier level).  A thread per (row, column); a row's TPI threads
+// read its entries as one broadcast and its neighbours' rows coalesced.
+// Arithmetic in binary64, the block stored as S.
+template <int TPI, typename S>
+__global__ __launch_bounds__(kThreads) void k_trsv_level(const int32_t* __restrict__ lrows,
+                                                         int count,
+                                                         const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ ci,
+                                                         const double* __restrict__ v,
+                                                         const double* __restrict__ dinv,
+                                                         S* __restrict__ X) {
+  const int64_t total = (int64_t)count * TPI;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = lrows[idx / TPI];
+    const int c = (int)(idx % TPI);
+    double acc = static_cast<double>(X[row * TPI + c]);
+    for (int e = rp[row]; e < rp[row + 1]; ++e)
+      acc -= v[e] * static_cast<double>(X[(int64_t)ci[e] * TPI + c]);
+    X[row * TPI + c] = static_cast<S>(acc * dinv[row]);
+  }
+}
+
 // out[r] = (ident0 ? X0[r] : 0) + sum_b X_b[r] C_b ; H_g = sum_r P_g[r]^t out[r].
 // P0X tells that P[0] is the same block as the first coefficient operand
 // (the first CGS pass of block m uses A U_{m-1} both ways); it is loaded once.
@@ -2731,6 +2757,17 @@ hipError_t launch_tsplit(const double* r, const int32_t* dom, S* Z, int64_t n, i
 }
 
 template <int TPI, typename S>
+hipError_t launch_trsv_level(const int32_t* lrows, int count, const int32_t* rp, const int32_t* ci,
+                             const double* v, const double* dinv, S* X, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int64_t work = (int64_t)count * TPI;
+  const int g = (int)std::min<int64_t>((work + kThreads - 1) / kThreads, 8192);
+  hipLaunchKernelGGL((k_trsv_level<TPI, S>), dim3(g), dim3(kThreads), 0, st, lrows, count, rp, ci,
+                     v, dinv, X);
+  return hipGetLastError();
+}
+
+template <int TPI, typename S>
 hipError_t launch_update_gram(int nu, int ng, bool ident0, bool write_out, int tail,
                               const UGArgs<S>& a, int grid, hipStream_t st) {
 #define ECG_UG(NU, NG, ID, WR, TL, P0X)                                                   \
@@ -2856,6 +2893,9 @@ hipError_t launch_unpack(const double* Xp, int TPI, double* X, int k, int64_t n,
 #define ECG_INST(TPI, S)                                                                   \
   template hipError_t launch_tsplit<TPI, S>(const double*, const int32_t*, S*, int64_t, int, \
                                             hipStream_t);                                  \
+  template hipError_t launch_trsv_level<TPI, S>(const int32_t*, int, const int32_t*,         \
+                                                const int32_t*, const double*, const double*, \
+                                                S*, hipStream_t);                          \
   template hipError_t launch_update_gram<TPI, S>(int, int, bool, bool, int, const UGArgs<S>&, \
                                                  int, hipStream_t);                        \
   template hipError_t launch_xr<TPI, S>(const XRArgs<S>&, int, hipStream_t);               \

@@ -23,6 +23,7 @@
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <utility>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -50,8 +51,8 @@ int fail(int code, const std::string& msg) {
       return fail(ECG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));       \
   } while (0)
 
-const char* kclass_names[ECG_K_COUNT] = {"resid",  "tsplit", "cgs_gram", "cgs_update", "spmm",
-                                         "xr_update", "gram", "update", "small"};
+const char* kclass_names[ECG_K_COUNT] = {"resid",     "tsplit", "cgs_gram", "cgs_update", "spmm",
+                                         "xr_update", "gram",   "update",   "small",      "precond"};
 
 struct Timed {
   int k;
@@ -78,6 +79,15 @@ struct ecg_ctx {
   // entry p; both NULL when the caller's order is kept
   int32_t* perm = nullptr;
   int32_t* emap = nullptr;
+  // block Jacobi preconditioner M = L L^t (ecg_set_preconditioner), in the
+  // solver's row order: strictly lower L and strictly upper L^t in CSR,
+  // 1 / diag(L), and the rows of every level of the two triangular solves
+  int prec = ECG_PREC_NONE;
+  int32_t *pl_rp = nullptr, *pl_ci = nullptr, *pu_rp = nullptr, *pu_ci = nullptr;
+  double *pl_v = nullptr, *pu_v = nullptr, *p_dinv = nullptr;
+  int32_t *lev_f = nullptr, *lev_b = nullptr;
+  std::vector<int> levp_f, levp_b;   // level offsets into lev_f / lev_b (host)
+  int64_t pl_nnz = 0;
   double* vals = nullptr;
   float* vals32 = nullptr;
   double* b = nullptr;
@@ -266,6 +276,8 @@ extern "C" void ecg_destroy(ecg_ctx* c) {
   };
   f(c->rowptr); f(c->colind); f(c->dom); f(c->vals); f(c->vals32);
   f(c->perm); f(c->emap);
+  f(c->pl_rp); f(c->pl_ci); f(c->pl_v); f(c->pu_rp); f(c->pu_ci); f(c->pu_v); f(c->p_dinv);
+  f(c->lev_f); f(c->lev_b);
   f(c->b); f(c->x); f(c->r); f(c->x2); f(c->r2);
   for (void* p : c->U) f(p);
   for (void* p : c->AU) f(p);
@@ -522,10 +534,9 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   ALLOC(c->cnext, double, 3 * (size_t)T2);
   ALLOC(c->dcoef, double, 2 * (size_t)T2);
   ALLOC(c->pre_rinv, double, (size_t)T2);
-  if (o.variant != ECG_SRECG) {
-    ALLOC(c->ctab, double, (size_t)c->nslot * T2);
-    ALLOC(c->dtab, double, (size_t)c->nslot * T2);
-  }
+  // CGS coefficient tables: SRE-CG2 / MSDO-CG, and the preconditioned forms
+  ALLOC(c->ctab, double, (size_t)std::max(c->nslot, 2) * T2);
+  ALLOC(c->dtab, double, (size_t)std::max(c->nslot, 2) * T2);
   ALLOC(c->status, DevStatus, 1);
   ALLOC(c->partials, double, (size_t)max_partials * L);
   ALLOC(c->groups, double, (size_t)ngroups * L);
@@ -724,26 +735,26 @@ struct Engine {
     return pass_update(m, (const S*)c->Zp, c->dtab, U(slot));
   }
 
-  // One CGS pass, first half: coefficients tab[p] = -R_p^{-1} R_p^{-t}
-  // (A U_p)^t X for every block p since the restart (slots 0 .. m-2).
-  int pass_gram(int m, const S* X, double* tab) {
+  // One CGS pass, first half: coefficients tab[i] = -R_p^{-1} R_p^{-t}
+  // (A U_p)^t X for the blocks p in slots sl[0 .. cnt-1].
+  int pass_gram_slots(const int* sl, int cnt, const S* X, double* tab) {
     constexpr int T2 = TPI * TPI;
     constexpr int CH = TPI == 64 ? 2 : 3;
     const double bb = c->blk_bytes();
     const double nt2 = (double)c->n * c->t * c->t;
     int rc;
-    for (int p0 = 0; p0 <= m - 2; p0 += CH) {
-      const int len = std::min(CH, m - 1 - p0);
+    for (int p0 = 0; p0 < cnt; p0 += CH) {
+      const int len = std::min(CH, cnt - p0);
       UGArgs<S> g{};
       g.X[0] = X;
-      for (int k = 0; k < len; ++k) g.P[k] = AU(p0 + k);
+      for (int k = 0; k < len; ++k) g.P[k] = AU(sl[p0 + k]);
       g.n = c->n;
       g.rc = c->rc();
       if ((rc = ug(ECG_K_GRAM, 1, len, true, false, g, (1.0 + len) * bb, 2.0 * nt2 * len)))
         return rc;
-      TailArgs ta = tail0(m);
+      TailArgs ta = tail0(0);
       for (int k = 0; k < len; ++k) {
-        ta.rinv_g[k] = rinv(p0 + k);
+        ta.rinv_g[k] = rinv(sl[p0 + k]);
         ta.coef_out[k] = tab + (size_t)(p0 + k) * T2;
       }
       ta.rinv_right = nullptr;
@@ -752,20 +763,20 @@ struct Engine {
     return ECG_OK;
   }
 
-  // Second half: out = X + sum_p U_p tab[p] (in place after the first chunk;
-  // out may be X).
-  int pass_update(int m, const S* X, const double* tab, S* out) {
+  // Second half: out = X + sum_i U_{sl[i]} tab[i] (in place after the first
+  // chunk; out may be X).
+  int pass_update_slots(const int* sl, int cnt, const S* X, const double* tab, S* out) {
     constexpr int T2 = TPI * TPI;
     constexpr int CH = TPI == 64 ? 2 : 3;
     const double bb = c->blk_bytes();
     const double nt2 = (double)c->n * c->t * c->t;
     int rc;
-    for (int p0 = 0; p0 <= m - 2; p0 += CH) {
-      const int len = std::min(CH, m - 1 - p0);
+    for (int p0 = 0; p0 < cnt; p0 += CH) {
+      const int len = std::min(CH, cnt - p0);
       UGArgs<S> u{};
       u.X[0] = p0 == 0 ? X : out;
       for (int k = 0; k < len; ++k) {
-        u.X[1 + k] = U(p0 + k);
+        u.X[1 + k] = U(sl[p0 + k]);
         u.C[1 + k] = tab + (size_t)(p0 + k) * T2;
       }
       u.out = out;
@@ -775,6 +786,75 @@ struct Engine {
         return rc;
     }
     return ECG_OK;
+  }
+
+  // The same against every block since the restart (block p in slot p - 1).
+  int pass_gram(int m, const S* X, double* tab) {
+    std::vector<int> sl(std::max(m - 1, 0));
+    for (int p = 0; p < m - 1; ++p) sl[p] = p;
+    return pass_gram_slots(sl.data(), m - 1, X, tab);
+  }
+  int pass_update(int m, const S* X, const double* tab, S* out) {
+    std::vector<int> sl(std::max(m - 1, 0));
+    for (int p = 0; p < m - 1; ++p) sl[p] = p;
+    return pass_update_slots(sl.data(), m - 1, X, tab, out);
+  }
+
+  // Z <- M^{-1} Z = L^{-t} L^{-1} Z for the block Jacobi preconditioner:
+  // level-scheduled triangular solves, in place.
+  int apply_minv(S* Z) {
+    Timed tm;
+    const double lvl = (double)(c->levp_f.size() + c->levp_b.size());
+    c->tstart(tm, ECG_K_PRECOND,
+              4.0 * c->blk_bytes() + 2.0 * c->pl_nnz * 12.0 + 8.0 * c->n + 0.0 * lvl,
+              4.0 * c->pl_nnz * c->t + 2.0 * c->n * c->t);
+    for (size_t l = 0; l + 1 < c->levp_f.size(); ++l)
+      HIP_TRY((launch_trsv_level<TPI, S>(c->lev_f + c->levp_f[l], c->levp_f[l + 1] - c->levp_f[l],
+                                         c->pl_rp, c->pl_ci, c->pl_v, c->p_dinv, Z, c->st)));
+    for (size_t l = 0; l + 1 < c->levp_b.size(); ++l)
+      HIP_TRY((launch_trsv_level<TPI, S>(c->lev_b + c->levp_b[l], c->levp_b[l + 1] - c->levp_b[l],
+                                         c->pu_rp, c->pu_ci, c->pu_v, c->p_dinv, Z, c->st)));
+    c->tstop(tm);
+    return ECG_OK;
+  }
+
+  // Split preconditioned s-step methods (Section 5): the first block after a
+  // (re)start is M^{-1} T(r); later blocks start from M^{-1} A U_{m-1} (the
+  // stored A-image without its R^{-1}: a triangular factor on the right only
+  // rescales the block within its span, which the A-orthonormalization
+  // absorbs), A-orthonormalized by CGS2 against the previous two blocks
+  // (SRE-CG) or every block since the restart (SRE-CG2), and MSDO-CG's first
+  // block of an iteration is M^{-1} T(r_{k-1}) against every earlier block.
+  int block_prec(int m, int slot, int p1, int p2, bool first) {
+    const double bb = c->blk_bytes();
+    int rc;
+    const bool split = m == 1 || (c->o.variant == ECG_MSDO && first);
+    S* Zp = (S*)c->Zp;
+    if (split) {
+      S* dst = m == 1 ? U(slot) : Zp;
+      Timed tm;
+      c->tstart(tm, ECG_K_TSPLIT, bb + 12.0 * c->n, 0.0);
+      HIP_TRY((launch_tsplit<TPI, S>(c->r, c->dom, dst, c->n, c->grid, c->st)));
+      c->tstop(tm);
+      if ((rc = apply_minv(dst))) return rc;
+      if (m == 1) return ECG_OK;
+    } else {
+      HIP_TRY(hipMemcpyAsync(Zp, AU(p1), (size_t)c->n * TPI * sizeof(S), hipMemcpyDeviceToDevice,
+                             c->st));
+      if ((rc = apply_minv(Zp))) return rc;
+    }
+    std::vector<int> sl;
+    if (c->o.variant == ECG_SRECG) {
+      if (m >= 3) sl.push_back(p2);
+      sl.push_back(p1);
+    } else {
+      for (int p = 0; p < m - 1; ++p) sl.push_back(p);
+    }
+    const int cnt = (int)sl.size();
+    if ((rc = pass_gram_slots(sl.data(), cnt, Zp, c->ctab))) return rc;
+    if ((rc = pass_update_slots(sl.data(), cnt, Zp, c->ctab, Zp))) return rc;
+    if ((rc = pass_gram_slots(sl.data(), cnt, Zp, c->dtab))) return rc;
+    return pass_update_slots(sl.data(), cnt, Zp, c->dtab, U(slot));
   }
 
   // s-step MSDO-CG (Section 3.2): the first block of an iteration after the
@@ -824,7 +904,10 @@ struct Engine {
   int block(int m, int slot, int p1, int p2, bool first, const Fold* fold) {
     const double bb = c->blk_bytes();
     const double nt2 = (double)c->n * c->t * c->t;
-    if (c->o.variant == ECG_MSDO && first && m >= 2) {
+    if (c->prec != ECG_PREC_NONE) {
+      int rc = block_prec(m, slot, p1, p2, first);
+      if (rc) return rc;
+    } else if (c->o.variant == ECG_MSDO && first && m >= 2) {
       int rc = msdo_first(m, slot);
       if (rc) return rc;
     } else if (c->o.variant != ECG_SRECG && m >= 4) {
@@ -1018,19 +1101,26 @@ struct Engine {
           // blocks after the first of an iteration carry the x/r
           // contribution of the block before them
           Fold f{};
-          if (i >= 1) {
+          if (i >= 1 && c->prec == ECG_PREC_NONE) {
             f.beta = beta(slots[i - 1]);
             f.x_in = i == 1 ? c->x : c->x2;
             f.r_in = i == 1 ? c->r : c->r2;
           }
-          if ((rc = block(m, slot, slot_of[1], slot_of[2], i == 0, i >= 1 ? &f : nullptr)))
+          const bool fold = i >= 1 && c->prec == ECG_PREC_NONE;
+          if ((rc = block(m, slot, slot_of[1], slot_of[2], i == 0, fold ? &f : nullptr)))
             return rc;
           slots[i] = slot;
           ++nblocks;
         }
-        // the last block's contribution; x2, r2 then hold the new iterate
-        if ((rc = xr(&slots[c->s - 1], 1, c->s == 1 ? c->x : c->x2, c->s == 1 ? c->r : c->r2)))
+        // the last block's contribution (the earlier ones were carried by the
+        // next block's first CGS kernel; with a preconditioner all s blocks
+        // here); x2, r2 then hold the new iterate
+        if (c->prec != ECG_PREC_NONE) {
+          if ((rc = xr(slots, c->s, c->x, c->r))) return rc;
+        } else if ((rc = xr(&slots[c->s - 1], 1, c->s == 1 ? c->x : c->x2,
+                            c->s == 1 ? c->r : c->r2))) {
           return rc;
+        }
         if ((rc = read_status(&h))) return rc;
         if (h.breakdown) {       // x, r stay the last completed iterate
           status = ECG_BREAKDOWN;
@@ -1358,6 +1448,167 @@ extern "C" int ecg_get_basis(ecg_ctx* c, double* V, double* AV) {
     (void)hipFree(dav);
   }
   if (e != hipSuccess) return fail(ECG_EDEVICE, std::string("get_basis: ") + hipGetErrorString(e));
+  return ECG_OK;
+}
+
+namespace {
+
+void free_prec(ecg_ctx* c) {
+  auto f = [](auto*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+  };
+  f(c->pl_rp); f(c->pl_ci); f(c->pl_v); f(c->pu_rp); f(c->pu_ci); f(c->pu_v); f(c->p_dinv);
+  f(c->lev_f); f(c->lev_b);
+  c->levp_f.clear();
+  c->levp_b.clear();
+  c->pl_nnz = 0;
+  c->prec = ECG_PREC_NONE;
+}
+
+// Rows grouped by level (level[i] from 0): rows of level l are
+// out[off[l] .. off[l+1]), increasing within a level.
+void bucket_levels(const std::vector<int>& level, std::vector<int32_t>& out, std::vector<int>& off) {
+  const int64_t n = (int64_t)level.size();
+  int nl = 0;
+  for (int v : level) nl = std::max(nl, v + 1);
+  off.assign(nl + 1, 0);
+  for (int v : level) off[v + 1]++;
+  for (int l = 0; l < nl; ++l) off[l + 1] += off[l];
+  std::vector<int> pos(off.begin(), off.end() - 1);
+  out.resize(n);
+  for (int64_t i = 0; i < n; ++i) out[pos[level[i]]++] = (int32_t)i;
+}
+
+}  // namespace
+
+extern "C" int ecg_set_preconditioner(ecg_ctx* c, int32_t kind, const int32_t* blocks) {
+  if (!c) return fail(ECG_EINVAL, "NULL context");
+  if (kind != ECG_PREC_NONE && kind != ECG_PREC_BJ_IC0) return fail(ECG_EINVAL, "bad kind");
+  free_prec(c);
+  if (kind == ECG_PREC_NONE) return ECG_OK;
+  if (!blocks) return fail(ECG_EINVAL, "blocks is NULL");
+  const int64_t n = c->n, nnz = c->nnz;
+  const bool dev = c->o.device_ptrs == 1;
+  // the solver's matrix, domains and row order on the host
+  std::vector<int32_t> rp(n + 1), ci(nnz), dom(n), perm, bl(n);
+  std::vector<double> av(nnz);
+  HIP_TRY(hipMemcpy(rp.data(), c->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(ci.data(), c->colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(av.data(), c->vals, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(dom.data(), c->dom, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  if (c->perm) {
+    perm.resize(n);
+    HIP_TRY(hipMemcpy(perm.data(), c->perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  }
+  std::vector<int32_t> bc;
+  const int32_t* bv = blocks;
+  if (dev) {
+    bc.resize(n);
+    HIP_TRY(hipMemcpy(bc.data(), blocks, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    bv = bc.data();
+  }
+  int32_t nb = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t b = bv[perm.empty() ? i : perm[i]];
+    if (b < 0) return fail(ECG_EINVAL, "negative preconditioner block");
+    bl[i] = b;
+    nb = std::max(nb, b + 1);
+  }
+  // every block inside one domain (then T and M^{-1} commute, Section 5)
+  std::vector<int32_t> bdom(nb, -1);
+  for (int64_t i = 0; i < n; ++i) {
+    if (bdom[bl[i]] < 0) bdom[bl[i]] = dom[i];
+    else if (bdom[bl[i]] != dom[i])
+      return fail(ECG_EINVAL, "preconditioner block " + std::to_string(bl[i]) +
+                                  " spans more than one domain");
+  }
+  // IC(0) of the block diagonal part, row by row in the solver's order:
+  // L_ij = (A_ij - sum_{k<j} L_ik L_jk) / L_jj over the pattern, L_ii =
+  // sqrt(A_ii - sum L_ik^2)
+  std::vector<int64_t> lp(n + 1, 0);
+  std::vector<int32_t> lc;
+  std::vector<double> lv, diag(n);
+  lc.reserve((size_t)(nnz - n) / 2 + 16);
+  lv.reserve((size_t)(nnz - n) / 2 + 16);
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t i = 0; i < n; ++i) {
+    row.clear();
+    double aii = 0.0;
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+      const int32_t j = ci[e];
+      if (j == i) aii += av[e];
+      else if (j < i && bl[j] == bl[i]) row.emplace_back(j, av[e]);
+    }
+    std::sort(row.begin(), row.end());
+    const int64_t base = (int64_t)lc.size();
+    for (auto& jv : row) {
+      const int32_t j = jv.first;
+      double acc = jv.second;
+      // sum over k < j in both row i (computed so far) and row j of L
+      int64_t a = base, b = lp[j];
+      const int64_t ae = (int64_t)lc.size(), be = lp[j + 1];
+      while (a < ae && b < be) {
+        if (lc[a] == lc[b]) acc -= lv[a++] * lv[b++];
+        else if (lc[a] < lc[b]) ++a;
+        else ++b;
+      }
+      lc.push_back(j);
+      lv.push_back(acc / diag[j]);
+    }
+    double d = aii;
+    for (int64_t a = base; a < (int64_t)lc.size(); ++a) d -= lv[a] * lv[a];
+    if (!(d > 0.0) || !std::isfinite(d))
+      return fail(ECG_EINVAL, "IC(0) pivot of row " + std::to_string(i) + " is not positive");
+    diag[i] = std::sqrt(d);
+    lp[i + 1] = (int64_t)lc.size();
+  }
+  const int64_t ln = (int64_t)lc.size();
+  if (ln >= (int64_t(1) << 31)) return fail(ECG_EINVAL, "factor too large");
+  // L^t (strictly upper) by rows
+  std::vector<int32_t> up(n + 1, 0), uc(ln);
+  std::vector<double> uv(ln);
+  for (int64_t a = 0; a < ln; ++a) up[lc[a] + 1]++;
+  for (int64_t i = 0; i < n; ++i) up[i + 1] += up[i];
+  {
+    std::vector<int32_t> pos(up.begin(), up.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t a = lp[i]; a < lp[i + 1]; ++a) {
+        uc[pos[lc[a]]] = (int32_t)i;
+        uv[pos[lc[a]]++] = lv[a];
+      }
+  }
+  // levels: forward over L, backward over L^t
+  std::vector<int> lf(n, 0), lb(n, 0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t a = lp[i]; a < lp[i + 1]; ++a) lf[i] = std::max(lf[i], lf[lc[a]] + 1);
+  for (int64_t i = n - 1; i >= 0; --i)
+    for (int32_t a = up[i]; a < up[i + 1]; ++a) lb[i] = std::max(lb[i], lb[uc[a]] + 1);
+  std::vector<int32_t> rows_f, rows_b;
+  bucket_levels(lf, rows_f, c->levp_f);
+  bucket_levels(lb, rows_b, c->levp_b);
+  std::vector<int32_t> lp32(n + 1);
+  std::vector<double> dinv(n);
+  for (int64_t i = 0; i <= n; ++i) lp32[i] = (int32_t)lp[i];
+  for (int64_t i = 0; i < n; ++i) dinv[i] = 1.0 / diag[i];
+  size_t tot = 0;
+  int rc = 0;
+  auto upl = [&](auto** dst, const auto& vec) -> int {
+    using T = typename std::remove_reference<decltype(vec)>::type::value_type;
+    int r = dalloc(dst, vec.size(), tot);
+    if (r) return r;
+    HIP_TRY(hipMemcpy(*dst, vec.data(), sizeof(T) * vec.size(), hipMemcpyHostToDevice));
+    return ECG_OK;
+  };
+  if ((rc = upl(&c->pl_rp, lp32)) || (rc = upl(&c->pl_ci, lc)) || (rc = upl(&c->pl_v, lv)) ||
+      (rc = upl(&c->pu_rp, up)) || (rc = upl(&c->pu_ci, uc)) || (rc = upl(&c->pu_v, uv)) ||
+      (rc = upl(&c->p_dinv, dinv)) || (rc = upl(&c->lev_f, rows_f)) ||
+      (rc = upl(&c->lev_b, rows_b))) {
+    free_prec(c);
+    return rc;
+  }
+  c->pl_nnz = ln;
+  c->prec = kind;
   return ECG_OK;
 }
 

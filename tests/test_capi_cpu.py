@@ -36,8 +36,8 @@ def test_version_and_strings():
     for code in (0, 1, 2, 3, -1, -2, -3, -4):
         assert E.strerror(code) and E.strerror(code) != "unknown status"
     assert E.strerror(99) == "unknown status"
-    assert [E.lib.ecg_kclass_name(i).decode() for i in range(9)] == E.KCLASSES
-    assert E.lib.ecg_kclass_name(9) is None
+    assert [E.lib.ecg_kclass_name(i).decode() for i in range(10)] == E.KCLASSES
+    assert E.lib.ecg_kclass_name(10) is None
 
 
 def test_opts_default():

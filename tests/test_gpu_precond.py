@@ -1,0 +1,107 @@
+"""GPU parity of the split preconditioned s-step methods (Section 5) with the
+block Jacobi IC(0) preconditioner, through the C ABI, against the float64
+oracle: iteration counts within 2, x within 1e-6, first iterates to 1e-10."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle as O
+import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    import paper_1804_10629_amd as E
+    return E
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _case(m, t, parts, blocks_parts):
+    p = P.poisson2d(m, t=t, parts=parts)
+    A = p.scipy()
+    dom = O.partition_grid(p.shape, parts)
+    blk = O.partition_grid(p.shape, blocks_parts)
+    L = O.block_jacobi_ic0(A, blk)
+    return p, A, dom, blk, O.apply_llt_inverse(L)
+
+
+@pytest.mark.parametrize("m,t,s,parts,bparts,variant", [
+    (100, 8, 2, (2, 4, 1), (8, 8, 1), "srecg"),
+    (100, 8, 4, (2, 4, 1), (8, 8, 1), "srecg"),
+    (60, 16, 3, (4, 4, 1), (8, 8, 1), "srecg2"),
+    (60, 16, 2, (4, 4, 1), (4, 4, 1), "msdo"),
+    (64, 64, 2, (8, 8, 1), (8, 8, 1), "srecg"),
+    (48, 30, 2, (6, 5, 1), (12, 10, 1), "srecg")])
+def test_preconditioned_parity(E, m, t, s, parts, bparts, variant):
+    p, A, dom, blk, M = _case(m, t, parts, bparts)
+    vmap = {"srecg": E.SRECG, "srecg2": E.SRECG2, "msdo": E.MSDO}
+    sol = E.Solver(p.rowptr, p.colind, p.vals, dom, t, s, variant=vmap[variant],
+                   precond_blocks=blk)
+    ref = O.sstep_srecg(A, dom, t, s, p.b, tol=1e-8, maxit=500, variant=variant, precond=M,
+                        record=True)
+    x, info = sol.solve(p.b, tol=1e-8, maxit=500)
+    assert info.status == E.OK and info.true_relres <= 1e-8
+    assert abs(info.iters - ref.iters) <= 2, (info.iters, ref.iters)
+    assert _rel(x.cpu().numpy(), ref.x) <= 1e-6
+    x1, _ = sol.solve(p.b, tol=1e-8, maxit=1)
+    assert _rel(x1.cpu().numpy(), ref.extra["xs"][1]) <= 1e-10
+    V, AV = sol.basis()
+    V = V.cpu().numpy()
+    Vr = ref.extra["V"][0][0]
+    assert np.abs(V - Vr).max() <= 1e-10 * np.abs(Vr).max()
+    sol.close()
+
+
+def test_preconditioner_cuts_iterations_and_can_be_removed(E):
+    p, A, dom, blk, M = _case(100, 8, (2, 4, 1), (8, 8, 1))
+    sol = E.Solver(p.rowptr, p.colind, p.vals, dom, 8, 2)
+    _, plain = sol.solve(p.b, tol=1e-8, maxit=500)
+    sol.set_preconditioner(E.PREC_BJ_IC0, blk)
+    _, pre = sol.solve(p.b, tol=1e-8, maxit=500)
+    assert pre.status == E.OK and pre.iters < 0.7 * plain.iters
+    sol.set_preconditioner(E.PREC_NONE)
+    _, again = sol.solve(p.b, tol=1e-8, maxit=500)
+    assert again.iters == plain.iters
+    st = sol.stats()
+    assert st["precond"]["launches"] == 0
+    sol.close()
+
+
+def test_preconditioned_mixed_precision(E):
+    p, A, dom, blk, M = _case(100, 8, (2, 4, 1), (8, 8, 1))
+    sol = E.Solver(p.rowptr, p.colind, p.vals, dom, 8, 2, precision=E.MIXED,
+                   precond_blocks=blk, collect_stats=True)
+    x, info = sol.solve(p.b, tol=1e-8, maxit=500)
+    ref = O.sstep_srecg(A, dom, 8, 2, p.b, tol=1e-8, maxit=500, precond=M)
+    assert info.status == E.OK and info.true_relres <= 1e-8
+    assert info.iters <= 1.3 * ref.iters + 2
+    print(f"mixed preconditioned: {info.iters} iterations (FP64 oracle {ref.iters}), "
+          f"|x - x_oracle|/|x_oracle| = {_rel(x.cpu().numpy(), ref.x):.2e}")
+    assert sol.stats()["precond"]["launches"] > 0
+    sol.close()
+
+
+def test_preconditioner_rejects_blocks_across_domains(E):
+    p, A, dom, blk, M = _case(40, 8, (2, 4, 1), (8, 8, 1))
+    sol = E.Solver(p.rowptr, p.colind, p.vals, dom, 8, 2)
+    bad = O.partition_grid(p.shape, (3, 1, 1))        # columns cut across domains
+    with pytest.raises(E.EcgError):
+        sol.set_preconditioner(E.PREC_BJ_IC0, bad)
+    with pytest.raises(E.EcgError):
+        sol.set_preconditioner(E.PREC_BJ_IC0, -np.ones(p.n, dtype=np.int32))
+    with pytest.raises(E.EcgError):
+        sol.set_preconditioner(7, blk)
+    # the context still solves without a preconditioner
+    _, info = sol.solve(p.b, tol=1e-8, maxit=500)
+    assert info.status == E.OK
+    sol.close()
