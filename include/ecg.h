@@ -42,7 +42,11 @@ extern "C" {
 #define ECG_OK          0  /* converged: true residual <= tol * ||b - A x0|| */
 #define ECG_MAXIT       1  /* iteration budget spent; x is the last iterate */
 #define ECG_BREAKDOWN   2  /* a Cholesky pivot of a basis Gram matrix was <= 0
-                              or not finite; x is the last completed iterate */
+                              or not finite in the first block after a
+                              (re)start (later blocks restart the solve from
+                              the last completed iterate, at most
+                              opts.max_restarts times); x is the last
+                              completed iterate */
 #define ECG_STAGNATED   3  /* the recursive residual met tol but the true
                               residual did not, after opts.max_restarts
                               residual replacements */

@@ -346,7 +346,8 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
                 orth="acholqr", aimage="stored", basis_dtype=np.float64,
                 inner_tol=0.0, max_restarts=20, q_cap_blocks=0,
                 record=False, stop_after_blocks: Optional[int] = None,
-                trace: Optional[list] = None, precond=None) -> SolveResult:
+                trace: Optional[list] = None, precond=None,
+                restart_on_breakdown=True) -> SolveResult:
     """s-step SRE-CG (variant='srecg') / s-step SRE-CG2 ('srecg2') / s-step
     MSDO-CG ('msdo', Section 3.2, algorithm "s-step MSDO-CG").
 
@@ -379,7 +380,14 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
         iterative-refinement step) whenever rho <= inner_tol * rho_restart;
       * SRE-CG2 and MSDO-CG keep all blocks since the last restart; when
         q_cap_blocks > 0 and another s blocks would exceed it, the solve
-        restarts from x.
+        restarts from x;
+      * a Cholesky breakdown in a block after the first one since the last
+        (re)start (a numerically rank-deficient block: the new directions
+        already lie in the basis, which a strong preconditioner makes
+        common near convergence) discards the iteration and restarts from
+        the last completed iterate (restart_on_breakdown, counted in
+        `restarts`, at most max_restarts); a breakdown in the first block
+        ends the solve with status BREAKDOWN.
 
     `precond` (optional) applies M^{-1} of a preconditioner M = L L^t to an
     n x t float64 block: the split preconditioned s-step methods of Section 5
@@ -420,6 +428,7 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
 
     blocks = new_store()
     fresh_start = True
+    m_since = 0             # blocks completed since the last (re)start
     xs = [x.copy()] if record else None
     rs = [r.copy()] if record else None
     Vs, alphas = [], []
@@ -437,6 +446,7 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
                 rho_restart = rho
                 fresh_start = True
                 blocks = new_store()
+                m_since = 0
                 continue
             V, AV = [], []
             try:
@@ -464,13 +474,26 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
                     V.append(W)
                     AV.append(AW)
                     nblocks += 1
+                    m_since += 1
                     if stop_after_blocks is not None and nblocks >= stop_after_blocks:
                         res.extra["last_blocks"] = (V, AV)
                         res.x, res.iters, res.blocks = x, k, nblocks
                         return res
             except Breakdown as e:
-                status = BREAKDOWN
                 res.extra["breakdown"] = str(e)
+                # READING: a breakdown after the first block since the last
+                # (re)start restarts from the last completed iterate
+                if restart_on_breakdown and m_since >= 1 and restarts < max_restarts:
+                    r = true_residual(A, b, x)
+                    rho = float(np.linalg.norm(r))
+                    hist.append(rho)
+                    restarts += 1
+                    rho_restart = rho
+                    fresh_start = True
+                    blocks = new_store()
+                    m_since = 0
+                    continue
+                status = BREAKDOWN
                 break
             Vm = _f64(np.hstack(V))
             AVm = _f64(np.hstack(AV))
@@ -507,6 +530,7 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
         rho_restart = tau
         fresh_start = True
         blocks = new_store()
+        m_since = 0
     res.x, res.iters, res.hist, res.status = x, k, hist, status
     res.restarts, res.blocks = restarts, nblocks
     res.true_relres = float(np.linalg.norm(b - A @ x)) / rho0

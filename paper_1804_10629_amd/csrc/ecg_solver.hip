@@ -1123,6 +1123,21 @@ struct Engine {
         }
         if ((rc = read_status(&h))) return rc;
         if (h.breakdown) {       // x, r stay the last completed iterate
+          if (h.breakdown_block >= 2 && restarts < c->o.max_restarts) {
+            // a rank-deficient block after the first one since the restart:
+            // restart from the last completed iterate
+            HIP_TRY(hipMemsetAsync(&c->status->breakdown, 0, 2 * sizeof(int), c->st));
+            if ((rc = resid(1))) return rc;
+            if ((rc = read_status(&h))) return rc;
+            rho = h.rho_true;
+            push(rho);
+            ++restarts;
+            progress("breakdown restart at", k, restarts, rho);
+            rho_restart = rho;
+            m = 0;
+            slot_of[0] = slot_of[1] = slot_of[2] = -1;
+            continue;
+          }
           status = ECG_BREAKDOWN;
           break;
         }

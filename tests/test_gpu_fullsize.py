@@ -129,3 +129,23 @@ def test_random_blocks_first_iteration_properties(E):
     assert drop <= 1e-10
     del V, AV, G
     sol.close()
+
+
+@pytest.mark.parametrize("cfg,mixed", [("C2", True), ("C5", False)])
+def test_block_jacobi_preconditioned_full_size(E, cfg, mixed):
+    # block Jacobi IC(0), blocks = the t domains: the full solve reaches the
+    # tolerance (at 128^3 in the mixed form the basis turns rank-deficient
+    # near convergence and the solve restarts from the last iterate); the
+    # true residual recomputed on the CPU in binary64
+    import torch
+    p = P.CONFIGS[cfg]()
+    sol, dom = _device_solver(E, p, precision=E.MIXED if mixed else E.FP64)
+    sol.set_preconditioner(E.PREC_BJ_IC0, dom)
+    x, info = sol.solve(torch.as_tensor(p.b).cuda(), tol=p.tol, maxit=1000)
+    xs = x.cpu().numpy()
+    true = float(np.linalg.norm(p.b - p.scipy() @ xs) / np.linalg.norm(p.b))
+    print(f"{cfg} preconditioned ({'mixed' if mixed else 'fp64'}): {info.iters} iterations, "
+          f"{info.restarts} restarts, true relres {true:.2e}")
+    assert info.status == E.OK and info.true_relres <= p.tol and true <= p.tol
+    assert info.iters <= (150 if cfg == "C5" else 100)
+    sol.close()

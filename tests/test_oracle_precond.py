@@ -148,3 +148,35 @@ def test_planted_unpreconditioned_first_block_is_caught(poisson):
     got = O.sstep_srecg(A, dom, 64, 2, p.b, tol=1e-6, maxit=60, precond=skip_first).iters
     want = _table()[("psre-cg", 64)][1]
     assert abs(got - want) > max(2, 0.10 * want)
+
+
+def test_breakdown_after_first_block_restarts():
+    # a rank-deficient block (a zero column) after the first block since the
+    # restart: the iteration is discarded and the solve restarts from the
+    # last completed iterate; in the first block it is a breakdown
+    p = P.poisson2d(40, t=4, parts=(2, 2, 1))
+    A = p.scipy()
+    dom = O.partition_grid(p.shape, p.parts)
+
+    def zero_column_at(call):
+        calls = {"n": 0}
+
+        def f(Z):
+            calls["n"] += 1
+            Z = np.array(Z, dtype=np.float64)
+            if calls["n"] == call:
+                Z[:, 1] = 0.0
+            return Z
+        return f
+    r = O.sstep_srecg(A, dom, 4, 2, p.b, tol=1e-8, precond=zero_column_at(3))
+    assert "breakdown" in r.extra and r.status == O.OK and r.restarts == 1
+    assert np.linalg.norm(p.b - A @ r.x) <= 1e-8 * np.linalg.norm(p.b)
+    # the restart re-splits the residual of the last completed iterate: the
+    # history holds that true residual right after iteration 1
+    assert abs(r.hist[2] - np.linalg.norm(p.b - A @ O.sstep_srecg(
+        A, dom, 4, 2, p.b, tol=1e-8, maxit=1).x)) <= 1e-12 * r.hist[0]
+    off = O.sstep_srecg(A, dom, 4, 2, p.b, tol=1e-8, precond=zero_column_at(3),
+                        restart_on_breakdown=False)
+    assert off.status == O.BREAKDOWN and off.iters == 1
+    first = O.sstep_srecg(A, dom, 4, 2, p.b, tol=1e-8, precond=zero_column_at(1))
+    assert first.status == O.BREAKDOWN and first.iters == 0 and first.restarts == 0
