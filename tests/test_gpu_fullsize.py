@@ -149,3 +149,103 @@ def test_block_jacobi_preconditioned_full_size(E, cfg, mixed):
     assert info.status == E.OK and info.true_relres <= p.tol and true <= p.tol
     assert info.iters <= (150 if cfg == "C5" else 100)
     sol.close()
+
+
+def _golden(cfg):
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        f"fullsize_{cfg}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"no oracle reference for {cfg} (tests/golden/make_fullsize.py)")
+    return dict(np.load(path))
+
+
+@pytest.mark.parametrize("cfg", ["C2", "C3", "C4"])
+def test_full_solve_parity_against_oracle(E, cfg):
+    # the full FP64 solve against the float64 oracle's (tests/golden): count
+    # within 2 (within the ulp-perturbed ensemble's band + 2 where the
+    # oracle's own count moves), x at 65536 seeded rows within 1e-6 of the
+    # oracle's (relative 2-norm over the sample; the ensemble's sampled
+    # spread, capped, where the count moves), the residual history, and the
+    # true residual recomputed on the CPU
+    import torch
+    from tests.parity import CAP_2, SPREAD_2
+    g = _golden(cfg)
+    p = P.CONFIGS[cfg]()
+    sol, _ = _device_solver(E, p)
+    x, info = sol.solve(torch.as_tensor(p.b).cuda(), tol=p.tol, maxit=30000)
+    xs = x.cpu().numpy()
+    true = float(np.linalg.norm(p.b - p.scipy() @ xs) / np.linalg.norm(p.b))
+    idx = g["idx"]
+    rel = float(np.linalg.norm(xs[idx] - g["xs"]) / np.linalg.norm(g["xs"]))
+    lo, hi = int(g["ens_iters"].min()), int(g["ens_iters"].max())
+    spread = float(g["ens_spread2"])
+    print(f"{cfg}: GPU {info.iters} iterations, oracle {int(g['iters'])} (ensemble {lo}..{hi}, "
+          f"sampled spread {spread:.1e}); sampled |x - x_or|/|x_or| = {rel:.2e}; "
+          f"true relres {true:.2e}")
+    assert info.status == E.OK and true <= p.tol and int(g["status"]) == 0
+    if hi - lo <= 2 and spread <= 1e-7:
+        assert abs(info.iters - int(g["iters"])) <= 2
+        assert rel <= 1e-6
+        n = min(len(info.hist), len(g["hist"]))
+        h_or, h_gpu = g["hist"][:n], info.hist[:n]
+        assert np.all(np.abs(h_gpu - h_or) <= 1e-6 * h_or)
+    else:
+        assert spread <= SPREAD_2
+        assert lo - 2 <= info.iters <= hi + 2
+        assert rel <= min(CAP_2, max(1e-6, 2.0 * spread))
+    sol.close()
+
+
+def test_differentiation_full_size(E):
+    # the differentiation form on the 1000^2 log-uniform problem: loss
+    # ||x - x_tgt||^2, forward and adjoint solves on the GPU, SDDMM bit-exact
+    # on all 4,996,000 stored entries, the adjoint residual recomputed on the
+    # CPU, and one symmetric entry pair against central differences
+    import time
+    import torch
+    p = P.CONFIGS["C4"]()
+    A = p.scipy()
+    sol, _ = _device_solver(E, p)
+    b = torch.as_tensor(p.b).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, fi = sol.solve(b, tol=1e-10, maxit=30000)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gx = 2.0 * (x - torch.as_tensor(p.extra["x_tgt"]).cuda())
+    lam, bi = sol.solve(gx, tol=1e-10, maxit=30000)
+    gA = sol.sddmm(lam, x)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    print(f"forward {t1 - t0:.2f} s ({fi.iters} iterations), backward {t2 - t1:.2f} s "
+          f"({bi.iters} iterations) incl. SDDMM")
+    assert fi.status == E.OK and bi.status == E.OK
+    xs, ls, gs = x.cpu().numpy(), lam.cpu().numpy(), gx.cpu().numpy()
+    assert np.linalg.norm(A @ ls - gs) <= 1e-9 * np.linalg.norm(gs)
+    assert np.array_equal(gA.cpu().numpy(), O.sddmm(p.rowptr, p.colind, ls, xs))
+    # dL/dA for the pair (i, j), (j, i) of an off-diagonal entry, against
+    # central differences of the loss with both entries moved together
+    rows = np.repeat(np.arange(p.n), np.diff(p.rowptr))
+    q = int(np.nonzero((rows == 500_500) & (p.colind == 500_501))[0][0])
+    qt = int(np.nonzero((rows == 500_501) & (p.colind == 500_500))[0][0])
+    an = float(gA[q] + gA[qt])
+    h = 1e-4 * abs(p.vals[q])
+    loss = []
+    for sgn in (1.0, -1.0):
+        v = p.vals.copy()
+        v[q] += sgn * h
+        v[qt] += sgn * h
+        s2 = E.Solver(p.rowptr, p.colind, v, O.partition_grid(p.shape, p.parts), p.t, p.s)
+        xv, iv = s2.solve(p.b, tol=1e-12, maxit=30000)
+        xv = xv.cpu().numpy()
+        # one step of iterative refinement in binary64 on the CPU
+        Av = O.csr(p.rowptr, p.colind, v)
+        d, _ = s2.solve(p.b - Av @ xv, tol=1e-6, maxit=30000)
+        xv = xv + d.cpu().numpy()
+        loss.append(float(np.sum((xv - p.extra["x_tgt"]) ** 2)))
+        s2.close()
+    fd = (loss[0] - loss[1]) / (2 * h)
+    print(f"dL/dA pair: adjoint {an:.6e}, central difference {fd:.6e}")
+    assert abs(fd - an) <= 1e-4 * max(abs(an), 1e-12)
+    sol.close()
