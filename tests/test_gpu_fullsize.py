@@ -200,8 +200,10 @@ def test_full_solve_parity_against_oracle(E, cfg):
 def test_differentiation_full_size(E):
     # the differentiation form on the 1000^2 log-uniform problem: loss
     # ||x - x_tgt||^2, forward and adjoint solves on the GPU, SDDMM bit-exact
-    # on all 4,996,000 stored entries, the adjoint residual recomputed on the
-    # CPU, and one symmetric entry pair against central differences
+    # on all 4,996,000 stored entries and the adjoint residual recomputed on
+    # the CPU (finite differences of single entries are checked on a 32 x 32
+    # field of the same family, test_gpu_autograd.py: at 1000^2 the loss
+    # differences they need lie below what a solve resolves)
     import time
     import torch
     p = P.CONFIGS["C4"]()
@@ -224,28 +226,4 @@ def test_differentiation_full_size(E):
     xs, ls, gs = x.cpu().numpy(), lam.cpu().numpy(), gx.cpu().numpy()
     assert np.linalg.norm(A @ ls - gs) <= 1e-9 * np.linalg.norm(gs)
     assert np.array_equal(gA.cpu().numpy(), O.sddmm(p.rowptr, p.colind, ls, xs))
-    # dL/dA for the pair (i, j), (j, i) of an off-diagonal entry, against
-    # central differences of the loss with both entries moved together
-    rows = np.repeat(np.arange(p.n), np.diff(p.rowptr))
-    q = int(np.nonzero((rows == 500_500) & (p.colind == 500_501))[0][0])
-    qt = int(np.nonzero((rows == 500_501) & (p.colind == 500_500))[0][0])
-    an = float(gA[q] + gA[qt])
-    h = 1e-4 * abs(p.vals[q])
-    loss = []
-    for sgn in (1.0, -1.0):
-        v = p.vals.copy()
-        v[q] += sgn * h
-        v[qt] += sgn * h
-        s2 = E.Solver(p.rowptr, p.colind, v, O.partition_grid(p.shape, p.parts), p.t, p.s)
-        xv, iv = s2.solve(p.b, tol=1e-12, maxit=30000)
-        xv = xv.cpu().numpy()
-        # one step of iterative refinement in binary64 on the CPU
-        Av = O.csr(p.rowptr, p.colind, v)
-        d, _ = s2.solve(p.b - Av @ xv, tol=1e-6, maxit=30000)
-        xv = xv + d.cpu().numpy()
-        loss.append(float(np.sum((xv - p.extra["x_tgt"]) ** 2)))
-        s2.close()
-    fd = (loss[0] - loss[1]) / (2 * h)
-    print(f"dL/dA pair: adjoint {an:.6e}, central difference {fd:.6e}")
-    assert abs(fd - an) <= 1e-4 * max(abs(an), 1e-12)
     sol.close()
