@@ -212,11 +212,11 @@ def test_differentiation_full_size(E):
     b = torch.as_tensor(p.b).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    x, fi = sol.solve(b, tol=1e-10, maxit=30000)
+    x, fi = sol.solve(b, tol=p.tol, maxit=30000)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     gx = 2.0 * (x - torch.as_tensor(p.extra["x_tgt"]).cuda())
-    lam, bi = sol.solve(gx, tol=1e-10, maxit=30000)
+    lam, bi = sol.solve(gx, tol=p.tol, maxit=30000)
     gA = sol.sddmm(lam, x)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
@@ -224,6 +224,6 @@ def test_differentiation_full_size(E):
           f"({bi.iters} iterations) incl. SDDMM")
     assert fi.status == E.OK and bi.status == E.OK
     xs, ls, gs = x.cpu().numpy(), lam.cpu().numpy(), gx.cpu().numpy()
-    assert np.linalg.norm(A @ ls - gs) <= 1e-9 * np.linalg.norm(gs)
+    assert np.linalg.norm(A @ ls - gs) <= 1.01 * p.tol * np.linalg.norm(gs)
     assert np.array_equal(gA.cpu().numpy(), O.sddmm(p.rowptr, p.colind, ls, xs))
     sol.close()
