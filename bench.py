@@ -17,11 +17,14 @@ they launch (operand bytes per launch, counted by the library) over the
 measured wall time.  The same is measured for the binary32-basis precision
 form.
 
-Time-to-1e-8 of the full solve: at 256^3 the solve takes about ten thousand
-s-step iterations (minutes), so it is measured by `python bench.py --full`
-(both forms, progress on stderr) and committed under profiles/; the default
-run measures the full time-to-1e-8 of the 128^3 skyscraper problem (t = 16,
-s = 4; seconds) in both forms as the `skyscraper_128` key.
+Time-to-1e-8 of the full solve: at 256^3 the unpreconditioned solve takes
+about ten thousand s-step iterations (minutes), so it is measured by
+`python bench.py --full` (both forms, progress on stderr) and committed under
+profiles/; every run measures the full time-to-1e-8 of the same 256^3 system
+with the split preconditioned method of Section 5 (block Jacobi, IC(0)
+blocks = the 64 domains; about sixty iterations) in both forms, and of the
+128^3 skyscraper problem (t = 16, s = 4; seconds) in both forms as the
+`skyscraper_128` key.
 
 Extra keys: the kernel table and roofline of the dominant kernel (from a
 separate solve with per-kernel HIP events on the solver's stream), and the
@@ -263,6 +266,34 @@ def full_solve(E, p, arrs, precision, maxit, form, progress_every=0):
                 "rel_err_vs_xstar": float(np.linalg.norm(xs - p.xstar) / np.linalg.norm(p.xstar))}
 
 
+def precond_solve(E, p, arrs, precision, maxit, form):
+    """Time-to-tolerance of the split preconditioned s-step SRE-CG with the
+    block Jacobi IC(0) preconditioner whose blocks are the t domains; the
+    host factorisation is timed separately."""
+    import torch
+    rp, ci, va, dom, bd = arrs
+    sol = E.Solver(rp, ci, va, dom, p.t, p.s, precision=precision)
+    t0 = time.perf_counter()
+    sol.set_preconditioner(E.PREC_BJ_IC0, dom)
+    torch.cuda.synchronize()
+    t_fact = time.perf_counter() - t0
+    sol.solve(bd, tol=p.tol, maxit=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info = sol.solve(bd, tol=p.tol, maxit=maxit)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sol.close()
+    xs = x.cpu().numpy()
+    log(f"[{form} + block Jacobi IC(0)] status {info.status}, {info.iters} iterations, "
+        f"{info.restarts} restarts, true relres {info.true_relres:.2e}, {wall:.2f} s "
+        f"(factorisation {t_fact:.2f} s)")
+    return {"time_s": round(wall, 4), "factorisation_s": round(t_fact, 3), "status": info.status,
+            "iters": info.iters, "restarts": info.restarts, "true_relres": info.true_relres,
+            "ms_per_iteration": round(wall * 1e3 / max(info.iters, 1), 2),
+            "rel_err_vs_xstar": float(np.linalg.norm(xs - p.xstar) / np.linalg.norm(p.xstar))}
+
+
 def both_forms_to_tolerance(E, p, maxit, progress_every=0):
     arrs = device_arrays(E, p)
     x64, f64 = full_solve(E, p, arrs, E.FP64, maxit, "fp64", progress_every)
@@ -334,6 +365,14 @@ def main():
     mixed = None
     if not args.no_mixed:
         mixed = iteration_form(E, p, arrs, E.MIXED, args.steps, args.warmup, "mixed")
+    prec = None
+    if not args.no_solve:
+        prec = {"preconditioner": "block Jacobi, IC(0) blocks = the t domains (Section 5)",
+                "workload": describe(p),
+                "fp64": precond_solve(E, p, arrs, E.FP64, args.maxit, "fp64")}
+        if not args.no_mixed:
+            prec["mixed"] = precond_solve(E, p, arrs, E.MIXED, args.maxit, "mixed")
+            prec["mixed"]["speedup_vs_fp64"] = round(prec["fp64"]["time_s"] / prec["mixed"]["time_s"], 3)
     del arrs
     torch.cuda.empty_cache()
 
@@ -378,7 +417,8 @@ def main():
             "kernels": mixed["kernels"],
             "roofline": roofline(mixed["kernels"], p.name, "mixed"),
         },
-        "time_to_1e8": {"source": "python bench.py --full (profiles/)", "in_this_run": False},
+        "time_to_1e8": {"unpreconditioned": "python bench.py --full (profiles/)",
+                        "block_jacobi_ic0": prec},
         "skyscraper_128": sky,
         "cpu_baseline": cpu,
     }
