@@ -36,6 +36,7 @@ FP64, MIXED = 0, 1
 KCLASSES = ["resid", "tsplit", "cgs_gram", "cgs_update", "spmm", "xr_update", "gram",
             "update", "small", "precond"]
 PREC_NONE, PREC_BJ_IC0 = 0, 1
+SPMM_NOALLOC_MAX = 4194304   # n x padded width limit of ecg_spmm_noalloc
 
 
 class EcgError(RuntimeError):
@@ -90,6 +91,7 @@ _SIGS = {
                                     ctypes.c_int32, ctypes.POINTER(_Result)]),
     "ecg_sddmm": (ctypes.c_int, [_P, _P, _P, _P]),
     "ecg_spmm": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
+    "ecg_spmm_noalloc": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
     "ecg_tsplit": (ctypes.c_int, [_P, _P, _P]),
     "ecg_get_basis": (ctypes.c_int, [_P, _P, _P]),
     "ecg_last_stats": (ctypes.c_int, [_P, ctypes.POINTER(_Stats)]),
@@ -290,6 +292,20 @@ class Solver:
         Y = torch.empty_like(Xd)
         _check(lib.ecg_spmm(self._ctx, Xd.data_ptr(), Y.data_ptr(), k))
         return Y
+
+    def spmm_noalloc(self, X, out):
+        """A X into the preallocated n x k float64 CUDA tensor `out`, through
+        ecg_spmm_noalloc (no device allocation inside the call; n times the
+        padded width of k must not exceed SPMM_NOALLOC_MAX)."""
+        torch = _torch()
+        if not (X.is_cuda and X.dtype == torch.float64 and X.is_contiguous()):
+            raise ValueError("X must be a contiguous float64 CUDA tensor")
+        if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+                and out.shape == X.shape):
+            raise ValueError("out must be a contiguous float64 CUDA tensor shaped like X")
+        k = 1 if X.dim() == 1 else int(X.shape[1])
+        _check(lib.ecg_spmm_noalloc(self._ctx, X.data_ptr(), out.data_ptr(), k))
+        return out
 
     def tsplit(self, r):
         """T(r) as an n x t float64 CUDA tensor."""

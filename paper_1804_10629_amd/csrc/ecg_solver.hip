@@ -27,6 +27,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -34,6 +35,12 @@
 #include "ecg.h"
 
 using namespace ecg;
+
+// Staging array of ecg_spmm_noalloc (two n x w blocks, 64 MiB), one copy per
+// GPU.  Its name is a host-side stand-in in host code: kernels get the
+// per-device address that resolve_noalloc_scratch records.
+constexpr size_t kNoAllocDoubles = 2 * (size_t)ECG_SPMM_NOALLOC_MAX;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
 
 namespace {
 
@@ -238,6 +245,32 @@ int check_device() {
   return ECG_OK;
 }
 
+// Per-device addresses of `scratch`: ecg_setup resolves each device's own
+// once, with that device current; ecg_spmm_noalloc uses only these.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// With device `dev` current: resolve (once) its address of `scratch`.
+int resolve_noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(ECG_EDEVICE, "device index " + std::to_string(dev) + " beyond the " +
+                                 std::to_string(kMaxDevices) + " the library tracks");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return ECG_OK;
+  void* p = nullptr;
+  HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) return fail(ECG_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+  g_scratch_ptr[dev] = (double*)p;
+  return ECG_OK;
+}
+
+double* noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
+
 // Copy `count` elements of an input array to host memory (device_ptrs mode).
 template <typename T>
 int fetch(const T* src, int64_t count, bool dev, std::vector<T>& out, const T** view) {
@@ -439,6 +472,11 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
 
   rc = check_device();
   if (rc) return rc;
+  {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if ((rc = resolve_noalloc_scratch(dev))) return rc;
+  }
 
   ecg_ctx* c = new ecg_ctx();
   c->n = n;
@@ -1380,6 +1418,46 @@ extern "C" int ecg_spmm(ecg_ctx* c, const double* X, double* Y, int32_t k) {
   } else {
     HIP_TRY(launch_unpack(c->scratch2, tpi, c->scratch, k, c->n, c->perm, c->st));
     HIP_TRY(hipMemcpyAsync(Y, c->scratch, sizeof(double) * c->n * k, hipMemcpyDeviceToHost, c->st));
+  }
+  HIP_TRY(hipStreamSynchronize(c->st));
+  return ECG_OK;
+}
+
+extern "C" int ecg_spmm_noalloc(ecg_ctx* c, const double* X, double* Y, int32_t k) {
+  if (!c || !X || !Y) return fail(ECG_EINVAL, "NULL argument");
+  if (k < 1 || k > 64) return fail(ECG_EINVAL, "k must be in [1, 64]");
+  const int tpi = pick_tpi(k);
+  if (c->n * tpi > (int64_t)ECG_SPMM_NOALLOC_MAX)
+    return fail(ECG_EINVAL, "ecg_spmm_noalloc: n x padded width = " + std::to_string(c->n) +
+                                " x " + std::to_string(tpi) + " exceeds ECG_SPMM_NOALLOC_MAX (" +
+                                std::to_string(ECG_SPMM_NOALLOC_MAX) + ")");
+  double* base = noalloc_scratch(c->dev);
+  if (!base) return fail(ECG_EDEVICE, "ecg_spmm_noalloc: no staging array for device " +
+                                          std::to_string(c->dev));
+  const bool dev = c->o.device_ptrs == 1;
+  const size_t blk = (size_t)c->n * tpi;
+  double* Xp = base;         // packed input, n x tpi (every entry written by the pack)
+  double* Yp = base + blk;   // product, n x tpi (every entry written by the product)
+  // host input: staged row-major n x k in Yp, which the product overwrites
+  // only after the pack has consumed it (stream order)
+  const double* Xin = X;
+  if (!dev) {
+    HIP_TRY(hipMemcpyAsync(Yp, X, sizeof(double) * c->n * k, hipMemcpyHostToDevice, c->st));
+    Xin = Yp;
+  }
+  HIP_TRY(launch_pack(Xin, k, Xp, tpi, c->n, c->perm, c->st));
+  int rc;
+  switch (tpi) {
+    case 16: rc = spmm_op<16>(c, Xp, Yp); break;
+    case 32: rc = spmm_op<32>(c, Xp, Yp); break;
+    default: rc = spmm_op<64>(c, Xp, Yp); break;
+  }
+  if (rc) return rc;
+  if (dev) {
+    HIP_TRY(launch_unpack(Yp, tpi, Y, k, c->n, c->perm, c->st));
+  } else {   // unpacked into Xp (free once the product has read it), then copied out
+    HIP_TRY(launch_unpack(Yp, tpi, Xp, k, c->n, c->perm, c->st));
+    HIP_TRY(hipMemcpyAsync(Y, Xp, sizeof(double) * c->n * k, hipMemcpyDeviceToHost, c->st));
   }
   HIP_TRY(hipStreamSynchronize(c->st));
   return ECG_OK;

@@ -129,6 +129,7 @@ def test_null_arguments():
     assert E.lib.ecg_solve_ex(None, None, None, 1e-8, 10, None, 0, None) == E.EINVAL
     assert E.lib.ecg_sddmm(None, None, None, None) == E.EINVAL
     assert E.lib.ecg_spmm(None, None, None, 4) == E.EINVAL
+    assert E.lib.ecg_spmm_noalloc(None, None, None, 4) == E.EINVAL
     assert E.lib.ecg_tsplit(None, None, None) == E.EINVAL
     assert E.lib.ecg_get_basis(None, None, None) == E.EINVAL
     assert E.lib.ecg_last_stats(None, None) == E.EINVAL
