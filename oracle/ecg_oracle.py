@@ -336,6 +336,47 @@ def srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, b: np.ndarray, x0=None,
     return SolveResult(x, k, hist, status, true_relres=tr)
 
 
+def _ca_arnoldi(Ab, blocks, r, dom, t, s, dtype, orthonormalize, *, split, aimage, precond):
+    """One iteration's basis by the modified CA-Arnoldi A-orthonormalization
+    (Section 4, algorithm "Modified CA-Arnoldi A-orthonormalization"; the
+    plain CA-Arnoldi of Section 3.1 differs only in skipping the first
+    block's own A-orthonormalization).  `blocks` holds Q and receives the s
+    new blocks.  Returns the lists of the s blocks of V and of A V."""
+    Q, AQ = blocks.all()
+    if split:
+        Z = split_T(r, dom, t)
+    elif aimage == "stored":
+        Z = blocks.last()[1].copy()
+    else:
+        Z = _spmm(Ab, blocks.last()[0], dtype)
+    if precond is not None:
+        Z = precond(_f64(Z))
+    Z = _store(Z, dtype)
+    # W_j: against Q, then against itself
+    Z = cgs2_a(Z, Q, AQ, dtype)
+    W, AW, _ = orthonormalize(Ab, Z, dtype)
+    # the monomial powers of W_j
+    powers = [W]
+    P = W
+    for i in range(1, s):
+        if i == 1 and aimage == "stored":
+            P = AW.copy()
+        else:
+            P = _spmm(Ab, P, dtype)
+        if precond is not None:
+            P = _store(precond(_f64(P)), dtype)
+        powers.append(P)
+    Vraw = np.hstack(powers)
+    # V: against Q, then against itself as one s t-column block
+    Vraw = cgs2_a(Vraw, Q, AQ, dtype)
+    V, AV, _ = orthonormalize(Ab, Vraw, dtype)
+    Vb = [V[:, i * t:(i + 1) * t] for i in range(s)]
+    AVb = [AV[:, i * t:(i + 1) * t] for i in range(s)]
+    for Wb, AWb in zip(Vb, AVb):
+        blocks.add(Wb, AWb)
+    return Vb, AVb
+
+
 # ---------------------------------------------------------------------------
 # s-step SRE-CG (Algorithm "s-step SRE-CG") and s-step SRE-CG2 (Algorithm
 # "s-step SRE-CG2"), with eqs (1)-(3) for the update
@@ -347,7 +388,7 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
                 inner_tol=0.0, max_restarts=20, q_cap_blocks=0,
                 record=False, stop_after_blocks: Optional[int] = None,
                 trace: Optional[list] = None, precond=None,
-                restart_on_breakdown=True) -> SolveResult:
+                restart_on_breakdown=True, ca=False) -> SolveResult:
     """s-step SRE-CG (variant='srecg') / s-step SRE-CG2 ('srecg2') / s-step
     MSDO-CG ('msdo', Section 3.2, algorithm "s-step MSDO-CG").
 
@@ -399,6 +440,21 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
     M^{-1} A W_{j-1}; alpha, x and r are updated with V and A V exactly as
     without a preconditioner.
 
+    ca=True builds each iteration's basis with the modified CA-Arnoldi
+    A-orthonormalization (Section 3.1 with Section 4, algorithm "Modified
+    CA-Arnoldi A-orthonormalization"): the CA SRE-CG, CA SRE-CG2 and (with
+    variant='msdo') CA MSDO-CG methods.  Per iteration, with Q the blocks
+    kept (the last s+1 for SRE-CG, all since the (re)start otherwise):
+    W_j is T(r) after a (re)start (and every iteration for MSDO-CG), else
+    A W_{j-1} of the last block; W_j is A-orthonormalized against Q (CGS2)
+    and itself (A-CholQR); the monomial powers A W_j, .., A^{s-1} W_j follow
+    (the matrix powers kernel); V = [W_j, A W_j, .., A^{s-1} W_j] is
+    A-orthonormalized against Q (CGS2) and then against itself as one
+    st-column block (A-CholQR of V, or Pre-CholQR).  READING: A W_j is the
+    stored A-image of W_j, A^i W_j (i >= 2) fresh products; with a
+    preconditioner every power is M^{-1} A times the previous one (Section
+    5).  The s blocks of V enter Q as s blocks of t columns.
+
     `trace` (a list, optional) receives one dict per block (the CGS2 output
     Z, A Z, the Gram G, R, W and A W) and one per true-residual check (x
     and its residual norm), for the precision pins.
@@ -423,8 +479,10 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
     k = 0
     restarts = 0
     nblocks = 0
+    keep = (s + 1 if ca else 2) if variant == "srecg" else None
+
     def new_store():
-        return _BlockStore(b.shape[0], dtype, 2 if variant == "srecg" else None)
+        return _BlockStore(b.shape[0], dtype, keep)
 
     blocks = new_store()
     fresh_start = True
@@ -450,7 +508,18 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
                 continue
             V, AV = [], []
             try:
-                for i in range(s):
+                if ca:
+                    V, AV = _ca_arnoldi(Ab, blocks, r, dom, t, s, dtype, orthonormalize,
+                                        split=fresh_start or variant == "msdo",
+                                        aimage=aimage, precond=precond)
+                    fresh_start = False
+                    nblocks += s
+                    m_since += s
+                    if stop_after_blocks is not None and nblocks >= stop_after_blocks:
+                        res.extra["last_blocks"] = (V, AV)
+                        res.x, res.iters, res.blocks = x, k, nblocks
+                        return res
+                for i in range(0 if not ca else s, s):
                     if fresh_start or (variant == "msdo" and i == 0):
                         Z = split_T(r, dom, t)
                         fresh_start = False

@@ -109,6 +109,23 @@ def read_msdo_table():
     return out
 
 
+CA_SVALS = [2, 3, 4, 5, 6, 7]
+
+
+def read_ca_table():
+    """Rows of tests/golden/poisson2d_ca_iterations.txt as
+    {(table, t): [counts for CA_SVALS, as far as printed]}."""
+    out = {}
+    with open(os.path.join(GOLDEN, "poisson2d_ca_iterations.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            parts = line.split()
+            out[(parts[0], int(parts[1]))] = [int(v) for v in parts[2:]]
+    return out
+
+
 # ---------------------------------------------------------------------------
 # The binary32-basis precision form
 # ---------------------------------------------------------------------------
