@@ -104,7 +104,17 @@ typedef struct ecg_opts {
                              device memory; every array argument and result
                              stays in the caller's order.  0: the caller's
                              order (default 1) */
-  int32_t reserved[4];    /* must be zero */
+  int32_t ca;             /* 1: build each iteration's basis with the modified
+                             CA-Arnoldi A-orthonormalization (Section 4):
+                             CA SRE-CG, CA SRE-CG2 or CA MSDO-CG by
+                             `variant`; the first block of an iteration is
+                             A-orthonormalized against the kept blocks and
+                             itself, then its monomial powers A W, ..,
+                             A^{s-1} W are formed and A-orthonormalized
+                             against the kept blocks and each other.  CA
+                             SRE-CG keeps the last s+1 blocks.  0: the s-step
+                             construction (default 0) */
+  int32_t reserved[3];    /* must be zero */
 } ecg_opts;
 
 /* Fill *o with the defaults above. */

@@ -24,9 +24,8 @@ import numpy as np
 import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# ECG_LIBRARY selects another build of the library (e.g. one with different
-# kernel tuning knobs); the default is the in-tree libecg.so
-LIB_PATH = os.environ.get("ECG_LIBRARY") or os.path.join(_HERE, "libecg.so")
+# always the in-tree build (paper_1804_10629_amd/build.py)
+LIB_PATH = os.path.join(_HERE, "libecg.so")
 
 OK, MAXIT, BREAKDOWN, STAGNATED = 0, 1, 2, 3
 EINVAL, ENOMEM, EDEVICE, ENOTSUP = -1, -2, -3, -4
@@ -53,7 +52,8 @@ class _Opts(ctypes.Structure):
         ("q_cap_blocks", ctypes.c_int32), ("ws_cap_bytes", ctypes.c_int64),
         ("hip_stream", ctypes.c_void_p), ("collect_stats", ctypes.c_int32),
         ("grid", ctypes.c_int32), ("progress_every", ctypes.c_int32),
-        ("permute_domains", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4),
+        ("permute_domains", ctypes.c_int32), ("ca", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -199,7 +199,8 @@ class SolveInfo:
 
 
 class Solver:
-    """s-step SRE-CG / SRE-CG2 solver for one sparse SPD matrix on the GPU.
+    """s-step SRE-CG / SRE-CG2 / MSDO-CG solver (ca=True: their CA forms)
+    for one sparse SPD matrix on the GPU.
 
     rowptr/colind/vals: CSR (int32, int32, float64), numpy arrays or torch
     tensors; partition: int32 domain index per row in [0, t).  Inputs are
@@ -211,7 +212,7 @@ class Solver:
                  inner_tol: float = 1e-4, max_restarts: int = 20, q_cap_blocks: int = 0,
                  ws_cap_bytes: int = 0, collect_stats: bool = False, grid: int = 0,
                  progress_every: int = 0, permute_domains: bool = True,
-                 precond_blocks=None):
+                 ca: bool = False, precond_blocks=None):
         torch = _torch()
         self._ctx = _P()
         o = _Opts()
@@ -222,6 +223,7 @@ class Solver:
         o.ws_cap_bytes, o.collect_stats, o.grid = ws_cap_bytes, int(collect_stats), grid
         o.progress_every = progress_every
         o.permute_domains = int(permute_domains)
+        o.ca = int(ca)
         o.hip_stream = _stream_ptr()
         self.opts = o
         rp = _dev_tensor(rowptr, torch.int32)

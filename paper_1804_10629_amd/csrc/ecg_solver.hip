@@ -375,7 +375,7 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   ecg_opts o;
   if (opts) o = *opts;
   else ecg_opts_default(&o);
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 3; ++i)
     if (o.reserved[i] != 0) return fail(ECG_EINVAL, "reserved option fields must be zero");
   if (!rowptr || !colind || !vals || !partition) return fail(ECG_EINVAL, "NULL array argument");
   if (n <= 0) return fail(ECG_EINVAL, "n must be positive");
@@ -390,6 +390,7 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   if (o.device_ptrs != 0 && o.device_ptrs != 1) return fail(ECG_EINVAL, "bad device_ptrs");
   if (o.permute_domains != 0 && o.permute_domains != 1)
     return fail(ECG_EINVAL, "bad permute_domains");
+  if (o.ca != 0 && o.ca != 1) return fail(ECG_EINVAL, "bad ca");
   if (!(o.inner_tol >= 0.0 && o.inner_tol < 1.0)) return fail(ECG_EINVAL, "inner_tol must be in [0, 1)");
   if (o.max_restarts < 0 || o.q_cap_blocks < 0 || o.ws_cap_bytes < 0 || o.grid < 0 ||
       o.progress_every < 0)
@@ -524,7 +525,9 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
     }
     c->nslot = (int)want;
   } else {
-    c->nslot = s + 2;
+    // s-step SRE-CG: blocks m-2 .. m of (s+2); CA SRE-CG: the s+1 kept
+    // blocks and the s of the iteration being built
+    c->nslot = o.ca ? 2 * s + 1 : s + 2;
   }
   double need = fixed + per_slot * c->nslot;
   if (need > cap) {
@@ -857,10 +860,9 @@ struct Engine {
   }
 
   // Split preconditioned s-step methods (Section 5): the first block after a
-  // (re)start is M^{-1} T(r); later blocks start from M^{-1} A U_{m-1} (the
-  // stored A-image without its R^{-1}: a triangular factor on the right only
-  // rescales the block within its span, which the A-orthonormalization
-  // absorbs), A-orthonormalized by CGS2 against the previous two blocks
+  // (re)start is M^{-1} T(r); later blocks start from M^{-1} A W_{m-1}
+  // (A W_{m-1} = A U_{m-1} R_{m-1}^{-1} formed by scale_into), A-orthonormalized
+  // by CGS2 against the previous two blocks
   // (SRE-CG) or every block since the restart (SRE-CG2), and MSDO-CG's first
   // block of an iteration is M^{-1} T(r_{k-1}) against every earlier block.
   int block_prec(int m, int slot, int p1, int p2, bool first) {
@@ -877,8 +879,7 @@ struct Engine {
       if ((rc = apply_minv(dst))) return rc;
       if (m == 1) return ECG_OK;
     } else {
-      HIP_TRY(hipMemcpyAsync(Zp, AU(p1), (size_t)c->n * TPI * sizeof(S), hipMemcpyDeviceToDevice,
-                             c->st));
+      if ((rc = scale_into(AU(p1), rinv(p1), Zp))) return rc;   // A W_{m-1}
       if ((rc = apply_minv(Zp))) return rc;
     }
     std::vector<int> sl;
@@ -931,6 +932,22 @@ struct Engine {
     u.X[0] = U(slot);
     u.C[0] = c->pre_rinv;
     u.out = U(slot);
+    u.n = c->n;
+    u.rc = c->rc();
+    return ug(ECG_K_UPDATE, 1, 0, false, true, u, 2.0 * bb, 2.0 * nt2);
+  }
+
+  // out = X R^{-1}: the A-image of an orthonormalized block from its stored
+  // unnormalized A-image (keeps the raw blocks of the preconditioned and CA
+  // forms at the scale of A W, not of a growing product of unnormalized
+  // blocks)
+  int scale_into(const S* X, const double* rinv_x, S* out) {
+    const double bb = c->blk_bytes();
+    const double nt2 = (double)c->n * c->t * c->t;
+    UGArgs<S> u{};
+    u.X[0] = X;
+    u.C[0] = rinv_x;
+    u.out = out;
     u.n = c->n;
     u.rc = c->rc();
     return ug(ECG_K_UPDATE, 1, 0, false, true, u, 2.0 * bb, 2.0 * nt2);
@@ -998,37 +1015,139 @@ struct Engine {
       HIP_TRY((launch_update_gram<TPI, S>(np + 1, 0, true, true, TAIL_NONE, kb, c->grid, c->st)));
       c->tstop(tm2);
     }
+    return cholqr(m, slot, m >= 2 ? p1 : -1);
+  }
+
+  // A-orthonormalize the CGS2 output in `slot` against itself (Pre-CholQR
+  // first when asked): the product A U with the Grams G, F, a = U^t r and,
+  // with the previous block in slot p1 >= 0, E; the tail forms R^{-1}, beta
+  // and the next block's first-pass coefficients.
+  int cholqr(int m, int slot, int p1) {
+    const double bb = c->blk_bytes();
+    const double nt2 = (double)c->n * c->t * c->t;
     if (c->o.orth == ECG_PRECHOLQR) {
       int rc = pre_cholqr(m, slot);
       if (rc) return rc;
     }
+    const bool prev = p1 >= 0;
     SpArgs<S, SA> sa{};
     sa.rowptr = c->rowptr;
     sa.colind = c->colind;
     sa.vals = avals();
     sa.Z = U(slot);
     sa.AZ = AU(slot);
-    sa.AZprev = m >= 2 ? AU(p1) : nullptr;
+    sa.AZprev = prev ? AU(p1) : nullptr;
     sa.rvec = c->r;
     sa.n = c->n;
     sa.max_row = c->max_row;
     sa.rc = c->rc();
     sa.tail = tail0(m);
     sa.tail.rinv_cur = rinv(slot);
-    sa.tail.rinv_p1 = m >= 2 ? rinv(p1) : nullptr;
+    sa.tail.rinv_p1 = prev ? rinv(p1) : nullptr;
     sa.tail.beta = beta(slot);
     Timed tm;
     const int vb = std::is_same<SA, float>::value ? 4 : 8;
     // algorithmic flops: the product, the upper triangles of the symmetric
     // Grams G and F (n t (t + 1) each), E in full, a = Z^t r
     const double ntt1 = (double)c->n * c->t * (c->t + 1);
-    c->tstart(tm, ECG_K_SPMM, c->csr_bytes(vb) + (m >= 2 ? 3.0 : 2.0) * bb + 8.0 * c->n,
-              2.0 * c->nnz * c->t + 2.0 * ntt1 + (m >= 2 ? 2.0 * nt2 : 0.0) +
+    c->tstart(tm, ECG_K_SPMM, c->csr_bytes(vb) + (prev ? 3.0 : 2.0) * bb + 8.0 * c->n,
+              2.0 * c->nnz * c->t + 2.0 * ntt1 + (prev ? 2.0 * nt2 : 0.0) +
                   2.0 * c->n * c->t);
-    HIP_TRY((launch_spmm<TPI, S, SA>(true, m >= 2, TAIL_SPMM, sa, c->grid, c->st)));
+    HIP_TRY((launch_spmm<TPI, S, SA>(true, prev, TAIL_SPMM, sa, c->grid, c->st)));
     c->tstop(tm);
     return reduce(spmm_partials(TPI, c->grid, c->max_row), 3 * TPI * TPI + TPI, TAIL_SPMM, 0,
                   sa.tail);
+  }
+
+  // out = A X with no Grams (one step of the matrix powers of the CA forms)
+  int power(const S* X, S* out) {
+    SpArgs<S, SA> sa{};
+    sa.rowptr = c->rowptr;
+    sa.colind = c->colind;
+    sa.vals = avals();
+    sa.Z = X;
+    sa.AZ = out;
+    sa.n = c->n;
+    sa.max_row = c->max_row;
+    sa.rc = c->rc();
+    Timed tm;
+    const int vb = std::is_same<SA, float>::value ? 4 : 8;
+    c->tstart(tm, ECG_K_SPMM, c->csr_bytes(vb) + 2.0 * c->blk_bytes(),
+              2.0 * c->nnz * c->t);
+    HIP_TRY((launch_spmm<TPI, S, SA>(false, false, TAIL_NONE, sa, c->grid, c->st)));
+    c->tstop(tm);
+    return ECG_OK;
+  }
+
+  // CGS2 of X against the blocks in slots sl into `out` (X and out may be
+  // the same block; with no blocks, a copy)
+  int cgs2_slots(const std::vector<int>& sl, const S* X, S* out) {
+    const int cnt = (int)sl.size();
+    S* Zp = (S*)c->Zp;
+    if (cnt == 0) {
+      if (X != out)
+        HIP_TRY(hipMemcpyAsync(out, X, (size_t)c->n * TPI * sizeof(S), hipMemcpyDeviceToDevice,
+                               c->st));
+      return ECG_OK;
+    }
+    int rc;
+    if ((rc = pass_gram_slots(sl.data(), cnt, X, c->ctab))) return rc;
+    if ((rc = pass_update_slots(sl.data(), cnt, X, c->ctab, Zp))) return rc;
+    if ((rc = pass_gram_slots(sl.data(), cnt, Zp, c->dtab))) return rc;
+    return pass_update_slots(sl.data(), cnt, Zp, c->dtab, out);
+  }
+
+  // The CA forms (Section 4, modified CA-Arnoldi A-orthonormalization):
+  // blocks m0+1 .. m0+s of one iteration into slots[0 .. s-1]; q holds the
+  // slots of the kept blocks (oldest first) and `last` the slot of the
+  // previous iteration's last block.
+  //   W_j: T(r) after a restart (every iteration for MSDO-CG), else
+  //        A W_{j-1} = A U_{j-1} R_{j-1}^{-1}; against q (CGS2), then A-CholQR.
+  //   powers: P_1 = A W_j from its stored A-image, P_i = A P_{i-1} (raw, in
+  //        the slots of blocks j+i): the matrix powers of W_j.
+  //   P_i: against q and W_j .. W_{j+i-1} (CGS2), then A-CholQR.  In exact
+  //        arithmetic this is the CGS2 of [W_j, P_1, ..] against q followed
+  //        by the A-CholQR of all s t columns at once, carried out block by
+  //        block so that every small factorization stays t x t.
+  // With a preconditioner every raw block is multiplied by M^{-1} (Section
+  // 5): M^{-1} T(r), M^{-1} A W_{j-1}, P_i = M^{-1} A P_{i-1}.
+  int ca_blocks(int m0, const int* slots, const std::vector<int>& q, int last) {
+    const double bb = c->blk_bytes();
+    const bool prec = c->prec != ECG_PREC_NONE;
+    const int s = c->s;
+    S* Zp = (S*)c->Zp;
+    int rc;
+    if (m0 == 0 || c->o.variant == ECG_MSDO) {
+      S* dst = q.empty() ? U(slots[0]) : Zp;
+      Timed tm;
+      c->tstart(tm, ECG_K_TSPLIT, bb + 12.0 * c->n, 0.0);
+      HIP_TRY((launch_tsplit<TPI, S>(c->r, c->dom, dst, c->n, c->grid, c->st)));
+      c->tstop(tm);
+      if (prec && (rc = apply_minv(dst))) return rc;
+      if (!q.empty() && (rc = cgs2_slots(q, Zp, U(slots[0])))) return rc;
+    } else {
+      if ((rc = scale_into(AU(last), rinv(last), Zp))) return rc;   // A W_{j-1}
+      if (prec && (rc = apply_minv(Zp))) return rc;
+      if ((rc = cgs2_slots(q, Zp, U(slots[0])))) return rc;
+    }
+    if ((rc = cholqr(m0 + 1, slots[0], -1))) return rc;
+    // the raw powers of W_j (all formed before any is orthogonalized):
+    // P_1 = A W_j = A U_j R_j^{-1}, P_i = A P_{i-1}
+    for (int i = 1; i < s; ++i) {
+      if (i == 1) {
+        if ((rc = scale_into(AU(slots[0]), rinv(slots[0]), U(slots[1])))) return rc;
+      } else if ((rc = power(U(slots[i - 1]), U(slots[i])))) {
+        return rc;
+      }
+      if (prec && (rc = apply_minv(U(slots[i])))) return rc;
+    }
+    std::vector<int> sl = q;
+    for (int i = 1; i < s; ++i) {
+      sl.push_back(slots[i - 1]);
+      if ((rc = cgs2_slots(sl, U(slots[i]), U(slots[i])))) return rc;
+      if ((rc = cholqr(m0 + 1 + i, slots[i], -1))) return rc;
+    }
+    return ECG_OK;
   }
 
   // x2 = x_in + sum U beta, r2 = r_in - sum AU beta over the given blocks, and ||r2||
@@ -1105,6 +1224,7 @@ struct Engine {
     int ns = c->nslot;
     const bool cg2 = c->o.variant != ECG_SRECG;   // every block since the restart is kept
     int slot_of[3] = {-1, -1, -1};   // slots of blocks m, m-1, m-2
+    std::vector<int> since;          // CA forms: slots of the blocks since the restart
     bool have_basis = false;
     while (true) {
       const double thr = std::max(inner * rho_restart, thr_final);
@@ -1127,10 +1247,29 @@ struct Engine {
           rho_restart = rho;
           m = 0;
           slot_of[0] = slot_of[1] = slot_of[2] = -1;
+          since.clear();
           continue;
         }
         int slots[kMaxS];
-        for (int i = 0; i < c->s; ++i) {
+        if (c->o.ca) {
+          // CA SRE-CG keeps the last s+1 blocks, the other forms all since
+          // the restart
+          const int kept = cg2 ? (int)since.size() : std::min((int)since.size(), c->s + 1);
+          const std::vector<int> q(since.end() - kept, since.end());
+          const int last = since.empty() ? -1 : since.back();
+          const int m0 = m;
+          for (int i = 0; i < c->s; ++i) {
+            ++m;
+            slots[i] = cg2 ? m - 1 : nblocks % ns;
+            ++nblocks;
+          }
+          if ((rc = ca_blocks(m0, slots, q, last))) return rc;
+          for (int i = 0; i < c->s; ++i) since.push_back(slots[i]);
+          if (!cg2 && (int)since.size() > c->s + 1)
+            since.erase(since.begin(), since.end() - (c->s + 1));
+          if ((rc = xr(slots, c->s, c->x, c->r))) return rc;
+        }
+        for (int i = 0; i < (c->o.ca ? 0 : c->s); ++i) {
           ++m;
           const int slot = cg2 ? m - 1 : nblocks % ns;
           slot_of[2] = slot_of[1];
@@ -1153,7 +1292,9 @@ struct Engine {
         // the last block's contribution (the earlier ones were carried by the
         // next block's first CGS kernel; with a preconditioner all s blocks
         // here); x2, r2 then hold the new iterate
-        if (c->prec != ECG_PREC_NONE) {
+        if (c->o.ca) {
+          // x/r done above over the s blocks
+        } else if (c->prec != ECG_PREC_NONE) {
           if ((rc = xr(slots, c->s, c->x, c->r))) return rc;
         } else if ((rc = xr(&slots[c->s - 1], 1, c->s == 1 ? c->x : c->x2,
                             c->s == 1 ? c->r : c->r2))) {
@@ -1174,6 +1315,7 @@ struct Engine {
             rho_restart = rho;
             m = 0;
             slot_of[0] = slot_of[1] = slot_of[2] = -1;
+            since.clear();
             continue;
           }
           status = ECG_BREAKDOWN;
@@ -1215,6 +1357,7 @@ struct Engine {
       rho_restart = tau;
       m = 0;
       slot_of[0] = slot_of[1] = slot_of[2] = -1;
+      since.clear();
     }
     (void)have_basis;
     // final true residual (the residual kernel leaves r = b - A x)

@@ -45,7 +45,8 @@ def test_opts_default():
     E.lib.ecg_opts_default(ctypes.byref(o))
     assert (o.variant, o.orth, o.precision, o.device_ptrs) == (0, 0, 0, 0)
     assert o.inner_tol == 1e-4 and o.max_restarts == 20 and o.grid == 0
-    assert list(o.reserved) == [0] * 4
+    assert list(o.reserved) == [0] * 3
+    assert o.ca == 0
     assert o.permute_domains == 1 and o.progress_every == 0
 
 
@@ -72,7 +73,8 @@ def small():
 
 @pytest.mark.parametrize("case", [
     "n0", "t0", "t65", "t_gt_n", "s0", "s17", "rowptr0", "decreasing", "col_range",
-    "part_range", "empty_domain", "nan_value", "reserved", "variant", "inner_tol", "q_cap"])
+    "part_range", "empty_domain", "nan_value", "reserved", "variant", "inner_tol", "q_cap",
+    "ca"])
 def test_setup_rejects(small, case):
     p, dom = small
     rp, ci, va, pd = p.rowptr.copy(), p.colind.copy(), p.vals.copy(), dom.copy()
@@ -103,13 +105,15 @@ def test_setup_rejects(small, case):
     elif case == "nan_value":
         va[10] = np.nan
     elif case == "reserved":
-        kw = {"reserved": (ctypes.c_int32 * 4)(0, 0, 1, 0)}
+        kw = {"reserved": (ctypes.c_int32 * 3)(0, 1, 0)}
     elif case == "variant":
         kw = {"variant": 7}
     elif case == "inner_tol":
         kw = {"inner_tol": 1.5}
     elif case == "q_cap":
         kw = {"variant": E.SRECG2, "q_cap_blocks": 1}
+    elif case == "ca":
+        kw = {"ca": 2}
     code, msg = _setup(n, rp, ci, va, pd, t, s, **kw)
     assert code == E.EINVAL, (case, code, msg)
     assert msg
