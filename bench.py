@@ -188,18 +188,32 @@ def cpu_baseline(p, gpu_bytes_per_iter):
     dt = time.perf_counter() - t0
     per_iter = dt * p.s / max(r.blocks, 1)
     hi = host_info()
+    one_core = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            O.sstep_srecg(A, dom, p.t, p.s, p.b, tol=p.tol, maxit=1, stop_after_blocks=1)
+            dt1 = time.perf_counter() - t1
+        per1 = dt1 * p.s / max(r.blocks, 1)
+        one_core = {"value": round(gpu_bytes_per_iter / per1 / 1e9, 3), "unit": "GB/s",
+                    "cores": 1, "s_per_iteration": round(per1, 2),
+                    "sample": "the same first block with the BLAS pool limited to one thread"}
+    except ImportError:
+        pass
     return {
         "value": round(gpu_bytes_per_iter / per_iter / 1e9, 3),
         "unit": "GB/s",
         "cores": blas_threads(),
         "kind": "oracle",
-        "sample": (f"oracle (numpy/scipy, float64) on the same {p.shape[0]}^3 problem stopped "
+        "sample": (f"oracle (numpy/scipy, float64) on the same {'x'.join(map(str, p.shape))} problem stopped "
                    f"after its first basis block ({dt:.1f} s: T(r), the sparse product, the "
                    f"Gram, Cholesky, two triangular solves); x {p.s} blocks = {per_iter:.1f} s "
                    f"per s-step iteration (an underestimate: later blocks add CGS2), over the "
                    f"GPU's algorithmic bytes per iteration; BLAS threads as 'cores', the "
                    f"sparse product single-threaded"),
         "s_per_iteration": round(per_iter, 2),
+        "one_core": one_core,
         "host": hi,
     }
 
@@ -332,7 +346,9 @@ def main():
     ap.add_argument("--config", default="C5", help="workload of the main line (C1..C5)")
     ap.add_argument("--maxit", type=int, default=30000, help="bound for full solves")
     ap.add_argument("--full", action="store_true",
-                    help="only the time-to-1e-8 of the main workload, both forms")
+                    help="only the time-to-1e-8 of the main workload (forms: --form)")
+    ap.add_argument("--form", choices=("both", "fp64", "mixed"), default="both",
+                    help="with --full: which form(s) to solve")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the full 128^3 skyscraper solves")
@@ -356,7 +372,13 @@ def main():
     p = build_problem(args.config)
     log(f"problem {describe(p)} ({time.perf_counter() - t0:.1f} s)")
     if args.full:
-        res = both_forms_to_tolerance(E, p, args.maxit, progress_every=100)
+        if args.form == "both":
+            res = both_forms_to_tolerance(E, p, args.maxit, progress_every=100)
+        else:
+            prec = E.FP64 if args.form == "fp64" else E.MIXED
+            _, one = full_solve(E, p, device_arrays(E, p), prec, args.maxit, args.form,
+                                progress_every=100)
+            res = {"workload": describe(p), args.form: one}
         print(json.dumps({"time_to_tolerance": res}), flush=True)
         return
 
