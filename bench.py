@@ -18,9 +18,9 @@ measured wall time.  The same is measured for the binary32-basis precision
 form.
 
 Time-to-1e-8 of the full solve: at 256^3 the unpreconditioned solve takes
-about ten thousand s-step iterations (minutes), so it is measured by
-`python bench.py --full` (both forms, progress on stderr) and committed under
-profiles/; every run measures the full time-to-1e-8 of the same 256^3 system
+about ten thousand s-step iterations (750 s FP64, 576 s mixed), so it is
+measured by `python bench.py --full --form fp64|mixed` (progress on stderr)
+and committed under profiles/; every run measures the full time-to-1e-8 of the same 256^3 system
 with the split preconditioned method of Section 5 (block Jacobi, IC(0)
 blocks = the 64 domains; about sixty iterations) in both forms, and of the
 128^3 skyscraper problem (t = 16, s = 4; seconds) in both forms as the
@@ -218,6 +218,34 @@ def cpu_baseline(p, gpu_bytes_per_iter):
     }
 
 
+def c1_full_solves(E):
+    """Time-to-1e-8 of the 100^2 Poisson problem (t = 8, s = 2) by the CPU
+    oracle on all BLAS threads and on one, and by the GPU (FP64)."""
+    import torch
+    import oracle as O
+    p = build_problem("C1")
+    A = p.scipy()
+    dom = O.partition_grid(p.shape, p.parts)
+    out = {"workload": describe(p)}
+    t0 = time.perf_counter()
+    r = O.sstep_srecg(A, dom, p.t, p.s, p.b, tol=p.tol)
+    out["oracle_all_threads"] = {"time_s": round(time.perf_counter() - t0, 3), "iters": r.iters,
+                                 "threads": blas_threads()}
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            r1 = O.sstep_srecg(A, dom, p.t, p.s, p.b, tol=p.tol)
+            out["oracle_one_thread"] = {"time_s": round(time.perf_counter() - t0, 3),
+                                        "iters": r1.iters, "threads": 1}
+    except ImportError:
+        pass
+    _, g = full_solve(E, p, device_arrays(E, p), E.FP64, 10000, "C1 fp64")
+    out["gpu_fp64"] = g
+    torch.cuda.empty_cache()
+    return out
+
+
 def device_arrays(E, p):
     import torch
     dom = E.partition_grid(p.shape, p.parts)
@@ -258,13 +286,14 @@ def iteration_form(E, p, arrs, precision, steps, warmup, form):
             "gbs": total_bytes / wall / 1e9, "kernels": kernel_table(stats)}
 
 
-def full_solve(E, p, arrs, precision, maxit, form, progress_every=0):
+def full_solve(E, p, arrs, precision, maxit, form, progress_every=0, **opts):
     """One warm-up solve of two iterations, then the full solve to the
-    tolerance, bracketed by device synchronisations."""
+    tolerance, bracketed by device synchronisations (`opts`: further
+    Solver options, e.g. the variant)."""
     import torch
     rp, ci, va, dom, bd = arrs
     sol = E.Solver(rp, ci, va, dom, p.t, p.s, precision=precision,
-                   progress_every=progress_every)
+                   progress_every=progress_every, **opts)
     sol.solve(bd, tol=p.tol, maxit=2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -317,6 +346,36 @@ def both_forms_to_tolerance(E, p, maxit, progress_every=0):
     return {"workload": describe(p), "fp64": f64, "mixed": mx}
 
 
+def variant_solves(E, cfgs, maxit, cap=64):
+    """Time-to-1e-8 of the variants the paper compares (Section 4; Tables
+    2-3), both forms: s-step SRE-CG, s-step SRE-CG2 with a cap of `cap`
+    blocks, Pre-CholQR, s-step MSDO-CG with the same cap, and the CA forms
+    of SRE-CG and SRE-CG2 (modified CA-Arnoldi)."""
+    import torch
+    table = [("sstep_srecg", {}),
+             ("sstep_srecg2_cap", {"variant": E.SRECG2, "q_cap_blocks": cap}),
+             ("sstep_srecg_precholqr", {"orth": E.PRECHOLQR}),
+             ("sstep_msdo_cap", {"variant": E.MSDO, "q_cap_blocks": cap}),
+             ("ca_srecg", {"ca": True}),
+             ("ca_srecg2_cap", {"variant": E.SRECG2, "ca": True, "q_cap_blocks": cap})]
+    out = {}
+    for cfg in cfgs:
+        p = build_problem(cfg)
+        log(f"problem {describe(p)}")
+        arrs = device_arrays(E, p)
+        rows = {"workload": describe(p), "block_cap": cap}
+        for name, kw in table:
+            rows[name] = {}
+            for form, prec in (("fp64", E.FP64), ("mixed", E.MIXED)):
+                log(f"[{cfg} {name} {form}]")
+                _, r = full_solve(E, p, arrs, prec, maxit, form, **kw)
+                rows[name][form] = r
+        out[cfg] = rows
+        del arrs
+        torch.cuda.empty_cache()
+    return out
+
+
 def calibrate(torch):
     """Plain device copy of 256 MiB: the practical streaming ceiling, and the
     known-size kernel against which FETCH_SIZE / WRITE_SIZE are scaled."""
@@ -349,6 +408,9 @@ def main():
                     help="only the time-to-1e-8 of the main workload (forms: --form)")
     ap.add_argument("--form", choices=("both", "fp64", "mixed"), default="both",
                     help="with --full: which form(s) to solve")
+    ap.add_argument("--variants", default="",
+                    help="comma-separated configs (e.g. C2,C3): only the time-to-1e-8 of the "
+                         "s-step, SRE-CG2, Pre-CholQR, MSDO-CG and CA variants there")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the full 128^3 skyscraper solves")
@@ -368,6 +430,11 @@ def main():
     if args.calibrate:
         calibrate(torch)
         return
+    if args.variants:
+        res = variant_solves(E, args.variants.split(","), args.maxit)
+        print(json.dumps({"variants_time_to_tolerance": res}), flush=True)
+        return
+
     t0 = time.perf_counter()
     p = build_problem(args.config)
     log(f"problem {describe(p)} ({time.perf_counter() - t0:.1f} s)")
@@ -409,6 +476,8 @@ def main():
     if not args.no_cpu_baseline:
         log("CPU oracle sample")
         cpu = cpu_baseline(p, bytes_per_iter)
+        log("C1 full solves: oracle and GPU")
+        cpu["c1_full_solves"] = c1_full_solves(E)
 
     out = {
         "metric": METRIC,
@@ -439,7 +508,8 @@ def main():
             "kernels": mixed["kernels"],
             "roofline": roofline(mixed["kernels"], p.name, "mixed"),
         },
-        "time_to_1e8": {"unpreconditioned": "python bench.py --full (profiles/)",
+        "time_to_1e8": {"unpreconditioned": ("python bench.py --full --form fp64|mixed; "
+                                             "profiles/randomblocks3d_256_time_to_1e8.md"),
                         "block_jacobi_ic0": prec},
         "skyscraper_128": sky,
         "cpu_baseline": cpu,

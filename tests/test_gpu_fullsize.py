@@ -5,7 +5,8 @@ benchmark uses (default grid, stream and options).
   the first s-step iteration is compared element by element with the
   oracle's (x_1 over all 2.1M rows; at 16 columns also the basis it built),
   in the FP64 and the mixed form.
-* 128^3 skyscraper: a full solve, its true residual recomputed on the CPU.
+* 128^3 skyscraper: a full solve, its true residual recomputed on the CPU,
+  and two 60-iteration solves in each form that agree bit for bit.
 * 256^3 random blocks (t = 64, s = 2, 16.8M rows): too large for the oracle;
   the first iteration is checked against properties that hold at any size
   (eqs (1)-(3) with an A-orthonormal basis): V^t A V = I, V^t r_1 = 0, and the
@@ -77,6 +78,23 @@ def test_skyscraper_full_solve(E, sky):
     # the true residual again, on the CPU in binary64
     assert np.linalg.norm(p.b - A @ x) <= p.tol * np.linalg.norm(p.b)
     assert np.linalg.norm(x - p.xstar) <= 1e-2 * np.linalg.norm(p.xstar)
+    sol.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_skyscraper_bitwise_reproducible(E, sky, mixed):
+    # fixed-order reductions: two solves of the same system give the same
+    # bits (x, every residual norm, the true residual)
+    p, _, _ = sky
+    sol, _ = _device_solver(E, p, precision=E.MIXED if mixed else E.FP64)
+    x1, i1 = sol.solve(p.b, tol=p.tol, maxit=60)
+    x1 = x1.cpu().numpy()
+    x2, i2 = sol.solve(p.b, tol=p.tol, maxit=60)
+    x2 = x2.cpu().numpy()
+    assert i1.iters == i2.iters == 60 and i1.restarts == i2.restarts
+    assert np.array_equal(x1, x2)
+    assert np.array_equal(np.asarray(i1.hist), np.asarray(i2.hist))
+    assert i1.true_relres == i2.true_relres
     sol.close()
 
 
