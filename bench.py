@@ -346,7 +346,7 @@ def both_forms_to_tolerance(E, p, maxit, progress_every=0):
     return {"workload": describe(p), "fp64": f64, "mixed": mx}
 
 
-def variant_solves(E, cfgs, maxit, cap=64):
+def variant_solves(E, cfgs, maxit, cap=64, only=None):
     """Time-to-1e-8 of the variants the paper compares (Section 4; Tables
     2-3), both forms: s-step SRE-CG, s-step SRE-CG2 with a cap of `cap`
     blocks, Pre-CholQR, s-step MSDO-CG with the same cap, and the CA forms
@@ -365,6 +365,8 @@ def variant_solves(E, cfgs, maxit, cap=64):
         arrs = device_arrays(E, p)
         rows = {"workload": describe(p), "block_cap": cap}
         for name, kw in table:
+            if only and name not in only:
+                continue
             rows[name] = {}
             for form, prec in (("fp64", E.FP64), ("mixed", E.MIXED)):
                 log(f"[{cfg} {name} {form}]")
@@ -411,6 +413,10 @@ def main():
     ap.add_argument("--variants", default="",
                     help="comma-separated configs (e.g. C2,C3): only the time-to-1e-8 of the "
                          "s-step, SRE-CG2, Pre-CholQR, MSDO-CG and CA variants there")
+    ap.add_argument("--cap", type=int, default=64,
+                    help="with --variants: blocks kept by SRE-CG2 / MSDO-CG before a restart")
+    ap.add_argument("--only", default="",
+                    help="with --variants: comma-separated variant names to run")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the full 128^3 skyscraper solves")
@@ -431,7 +437,8 @@ def main():
         calibrate(torch)
         return
     if args.variants:
-        res = variant_solves(E, args.variants.split(","), args.maxit)
+        res = variant_solves(E, args.variants.split(","), args.maxit, args.cap,
+                             [v for v in args.only.split(",") if v])
         print(json.dumps({"variants_time_to_tolerance": res}), flush=True)
         return
 

@@ -5,6 +5,7 @@ benchmark uses (default grid, stream and options).
   the first s-step iteration is compared element by element with the
   oracle's (x_1 over all 2.1M rows; at 16 columns also the basis it built),
   in the FP64 and the mixed form.
+* 128^3 anisotropic, CA SRE-CG: the first two iterates against the oracle.
 * 128^3 skyscraper: a full solve, its true residual recomputed on the CPU,
   and two 60-iteration solves in each form that agree bit for bit.
 * 256^3 random blocks (t = 64, s = 2, 16.8M rows): too large for the oracle;
@@ -95,6 +96,25 @@ def test_skyscraper_bitwise_reproducible(E, sky, mixed):
     assert np.array_equal(x1, x2)
     assert np.array_equal(np.asarray(i1.hist), np.asarray(i2.hist))
     assert i1.true_relres == i2.true_relres
+    sol.close()
+
+
+def test_ca_first_iterations_full_size(E):
+    # CA SRE-CG (modified CA-Arnoldi) at 128^3, t = 32, s = 4: the first two
+    # iterates over all 2.1M rows against the oracle (the second one
+    # A-orthonormalizes against the kept blocks)
+    p = P.CONFIGS["C3"]()
+    A = p.scipy()
+    dom = O.partition_grid(p.shape, p.parts)
+    ref = O.sstep_srecg(A, dom, p.t, p.s, p.b, tol=p.tol, maxit=2, ca=True, record=True)
+    sol, _ = _device_solver(E, p, ca=True)
+    for k in (1, 2):
+        x, info = sol.solve(p.b, tol=p.tol, maxit=k)
+        assert info.iters == k and info.blocks == k * p.s
+        xr = ref.extra["xs"][k]
+        rel = float(np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr))
+        print(f"CA SRE-CG 128^3 x_{k}: rel {rel:.2e}")
+        assert rel <= 1e-9
     sol.close()
 
 
