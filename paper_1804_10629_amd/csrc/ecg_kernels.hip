@@ -2129,20 +2129,34 @@ void k_spmm64(SpArgs<S, SA> a) {
   }
 }
 
-// Producer/consumer form of the 64-column product (12 waves per work-group,
-// one work-group per CU).  Waves 0-7 (producers) gather: wave w forms rows
-// 2 w, 2 w + 1 of each 16-row step as above, with the neighbour rows of a
+// Producer/consumer form of the 64-column product (16 waves per work-group,
+// one work-group per CU).  Waves 0-11 (producers) gather: wave w forms rows
+// 2 w, 2 w + 1 of each 24-row step as above, with the neighbour rows of a
 // step requested two steps ahead (the (column, value) pairs three steps
 // ahead, the row pointers four; two steps of requests stay within the 63
 // vector-memory instructions a wave can have in flight), and park the
-// step's Z, A Z and A Z_prev rows in an LDS slot.  Waves 8-11 (consumers)
+// step's Z, A Z and A Z_prev rows in an LDS slot.  Waves 12-15 (consumers)
 // run the Gram tiles on the matrix cores, one step behind: iteration i
 // produces step i into slot i % 2 while the consumers read step i - 1 from
 // the other slot, so one barrier per iteration orders both and the matrix
-// cores do not wait for a gather.  Each SIMD holds two producer waves and
+// cores do not wait for a gather.  Each SIMD holds three producer waves and
 // one consumer wave: their VALU / memory and MFMA instructions co-issue.
+// The gather is latency-bound, so more producers mean more rows in flight
+// (measured at 256^3: 8 producers and 16-row steps 11.75 ms, 12 and 24 rows
+// 10.05 ms per launch; 16 producers would exceed 1024 threads).
 #ifndef ECG_PC_R
-#define ECG_PC_R 16
+#define ECG_PC_R 24
+#endif
+// Step order: 1 = each XCD sweeps its own contiguous eighth of the steps
+// (its work-groups interleaved), 0 = all work-groups sweep the rows together
+// with the XCDs side by side.  With 16-row steps and 256 work-groups the
+// latter advances 4096 rows per round, the distance of a z-neighbour in a
+// 64^3 domain, so every XCD met its neighbours in its own L2; 24-row steps
+// break that (measured at 256^3: FETCH 38.4 GB per launch with 0, 33.4 GB
+// with 1, against 21.9 GB for 16-row steps), and 1 does not depend on the
+// geometry.
+#ifndef ECG_PC_MAP
+#define ECG_PC_MAP 1
 #endif
 #ifndef ECG_PC_PR
 #define ECG_PC_PR 2
@@ -2333,19 +2347,27 @@ __device__ __forceinline__ void p64pc_producer(const SpArgs<S, SA>& a, double* t
 }
 
 template <typename S, typename SA, bool HAS_PREV>
-__global__ __launch_bounds__(kP64THREADS) __attribute__((amdgpu_waves_per_eu(3, 3)))
+__global__ __launch_bounds__(kP64THREADS) __attribute__((amdgpu_waves_per_eu(kP64THREADS / 256, kP64THREADS / 256)))
 void k_spmm64pc(SpArgs<S, SA> a) {
   constexpr int T2 = 64 * 64;
   __shared__ double tiles[2 * 3 * kPCR * kP64LD];
   __shared__ double asum[kP64NP * 64];
   const int wave = threadIdx.x >> 6;
-  // all work-groups sweep the rows together, the 1/8 of them on one XCD
-  // taking adjacent steps (G / 8 steps of 16 rows per XCD and round)
   const int64_t nsteps = (a.n + kPCR - 1) / kPCR;
   const int G = gridDim.x;
+#if ECG_PC_MAP == 1
+  // each XCD sweeps its own contiguous eighth of the steps
+  const int64_t x8 = blockIdx.x % 8;
+  const Steps sp = (G % 8 == 0) ? Steps{x8 * nsteps / 8 + blockIdx.x / 8, (x8 + 1) * nsteps / 8,
+                                        G / 8}
+                                : Steps{blockIdx.x, nsteps, G};
+#else
+  // all work-groups sweep the rows together, the 1/8 of them on one XCD
+  // taking adjacent steps (G / 8 steps per XCD and round)
   const Steps sp = (G % 8 == 0) ? Steps{(int64_t)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8,
                                         nsteps, G}
                                 : Steps{blockIdx.x, nsteps, G};
+#endif
   const int N = sp.first < sp.end ? (int)((sp.end - sp.first + sp.stride - 1) / sp.stride) : 0;
   switch (wave - kP64NP) {
     case 0: p64pc_consumer<S, SA, HAS_PREV, 0>(a, tiles, N); break;
