@@ -67,12 +67,16 @@ def merge(cfg: str) -> str:
     iters = np.array([int(m["iters"]) for m in ms])
     xs = np.array([m["xs"] for m in ms])
     spread = max(float(np.linalg.norm(x - ref["xs"]) / np.linalg.norm(ref["xs"])) for x in xs)
+    # each member's sampled error against the exact solution x* of b = A x*
+    xstar = P.CONFIGS[cfg]().xstar[ref["idx"]]
+    err = np.array([float(np.linalg.norm(x - xstar) / np.linalg.norm(xstar)) for x in xs])
     out = os.path.join(HERE, f"fullsize_{cfg}.npz")
     np.savez_compressed(out, iters=ref["iters"], status=ref["status"], restarts=ref["restarts"],
                         hist=ref["hist"], true_relres=ref["true_relres"], xnorm=ref["xnorm"],
                         idx=ref["idx"], xs=ref["xs"], ens_iters=iters, ens_spread2=spread,
-                        seconds=np.array([float(m["seconds"]) for m in ms]))
-    print(f"{cfg}: members {iters.tolist()}, sampled 2-norm spread {spread:.2e} -> {out}")
+                        ens_err_xstar=err, seconds=np.array([float(m["seconds"]) for m in ms]))
+    print(f"{cfg}: members {iters.tolist()}, sampled 2-norm spread {spread:.2e}, "
+          f"sampled error vs x* {err.min():.2e} .. {err.max():.2e} -> {out}")
     return out
 
 

@@ -28,6 +28,11 @@ import oracle as O
 # problems are 1.3e-7 .. 6.0e-7 (A-norm) and 4.3e-5 .. 1.3e-4 (2-norm)
 SPREAD_A, CAP_A = 2.5e-6, 5e-6
 SPREAD_2, CAP_2 = 2.5e-4, 5e-4
+# the same bounds for the full-size references (tests/golden/fullsize_*.npz),
+# where only sampled rows of x are stored (no A-norm) and the longer solves
+# spread further: the 128^3 skyscraper ensemble ends at 982 .. 1130
+# iterations with a sampled 2-norm spread of 5.1e-4
+SPREAD_2_FULL, CAP_2_FULL = 1e-3, 2e-3
 
 
 def oracle_ensemble(A, dom, t, s, b, *, k=5, tol=1e-8, seed=0, **kw):
