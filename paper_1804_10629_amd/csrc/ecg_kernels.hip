@@ -1702,7 +1702,7 @@ template <int TPI, typename S, int NU, int NG, bool IDENT0, bool WRITE, bool P0X
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ECG_MF_WPE, ECG_MF_WPE)))
 void k_update_gram_mf(UGArgs<S> a) {
   constexpr int T2 = TPI * TPI, LD = TPI + 1;   // LD: padded tile rows
-  constexpr int W = TPI / 16, RG = 4 / W, KQ = TPI / 4;
+  constexpr int W = TPI / 16, RG = 4 / W, KQ = TPI / 4, NV = 4 / W;
   constexpr int NCOEF = NU - (IDENT0 ? 1 : 0);
   constexpr int NX = NU;
   constexpr int NP = NG - (P0X ? 1 : 0);
@@ -1743,8 +1743,10 @@ void k_update_gram_mf(UGArgs<S> a) {
   // binary64 kernels with Grams, slower for the binary64 pure updates, no
   // gain at 64 columns; at 16 columns only binary32 blocks take this kernel)
   constexpr bool PF = ECG_MF_PF && ((TPI == 32 && (sizeof(S) == 4 || NG > 0)) || TPI == 16);
-  // x and r: lane l takes row 4 (l % 4) + l / 16 of the 16 (lanes l % 16 >= 4
-  // repeat those rows), so one instruction covers the row group's rows
+  // x and r: the fold's rows are shared out over the row group's W waves,
+  // NV = 4 / W row quads each; lane l of wave cb takes row 4 vq + l / 16 with
+  // vq = cb + W (l % NV), so one instruction covers the wave's rows (lanes
+  // l % 16 >= NV repeat them)
   struct Ld {
     double c[NLD][4];
     double xo, ro;
@@ -1765,7 +1767,7 @@ void k_update_gram_mf(UGArgs<S> a) {
       for (int b = 0; b < NLD; ++b) d.c[b][v] = ld(src[b] + rc * TPI + 16 * cb + m) * okf;
     }
     if constexpr (FOLDK) {
-      const int64_t row = r0 + 4 * (m & 3);
+      const int64_t row = r0 + 4 * (cb + W * (m % NV));
       const int64_t rc = row < n ? row : n - 1;
       d.xo = xsrc[rc * xstride];
       d.ro = rsrc[rc * xstride];
@@ -1823,11 +1825,13 @@ void k_update_gram_mf(UGArgs<S> a) {
       });
     }
     if constexpr (!IDENT0 && NU >= 2) {
-      // x/r contribution of the previous block (X[1] = U, X[0] = A U): the
-      // row group's first wave reads the full rows from the tiles
-      if (fold && cb == 0) {
-        double dxm = 0.0, drm = 0.0;   // sums of row 4 (m % 4) + rq
-        for (int v = 0; v < 4; ++v) {
+      // x/r contribution of the previous block (X[1] = U, X[0] = A U): wave
+      // cb of the row group reads the full rows 4 vq + rq, vq = cb + W k,
+      // from the tiles (all waves share the work)
+      if (fold) {
+        double dxm = 0.0, drm = 0.0;   // sums of row 4 (cb + W (m % NV)) + rq
+        for (int k = 0; k < NV; ++k) {
+          const int v = cb + W * k;
           double dx = 0.0, dr = 0.0;
           for (int e = 0; e < W; ++e) {
             const double bv = fbeta[16 * e + m];
@@ -1836,11 +1840,11 @@ void k_update_gram_mf(UGArgs<S> a) {
           }
           dx = row_sum16(dx);
           dr = row_sum16(dr);
-          dxm = (m & 3) == v ? dx : dxm;
-          drm = (m & 3) == v ? dr : drm;
+          dxm = (m % NV) == k ? dx : dxm;
+          drm = (m % NV) == k ? dr : drm;
         }
-        const int64_t row = row0 + 4 * (m & 3);
-        if (m < 4 && row < n) {
+        const int64_t row = row0 + 4 * (cb + W * (m % NV));
+        if (m < NV && row < n) {
           a.x_out[row] = ldc.xo + dxm;
           a.r_out[row] = ldc.ro - drm;
         }
