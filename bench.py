@@ -18,7 +18,7 @@ measured wall time.  The same is measured for the binary32-basis precision
 form.
 
 Time-to-1e-8 of the full solve: at 256^3 the unpreconditioned solve takes
-about ten thousand s-step iterations (750 s FP64, 576 s mixed), so it is
+about ten thousand s-step iterations (712 s FP64, 547 s mixed), so it is
 measured by `python bench.py --full --form fp64|mixed` (progress on stderr)
 and committed under profiles/; every run measures the full time-to-1e-8 of the same 256^3 system
 with the split preconditioned method of Section 5 (block Jacobi, IC(0)
