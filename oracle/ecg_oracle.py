@@ -336,12 +336,15 @@ def srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, b: np.ndarray, x0=None,
     return SolveResult(x, k, hist, status, true_relres=tr)
 
 
-def _ca_arnoldi(Ab, blocks, r, dom, t, s, dtype, orthonormalize, *, split, aimage, precond):
+def _ca_arnoldi(Ab, blocks, r, dom, t, s, dtype, orthonormalize, *, split, aimage, precond,
+                plain=False):
     """One iteration's basis by the modified CA-Arnoldi A-orthonormalization
-    (Section 4, algorithm "Modified CA-Arnoldi A-orthonormalization"; the
-    plain CA-Arnoldi of Section 3.1 differs only in skipping the first
-    block's own A-orthonormalization).  `blocks` holds Q and receives the s
-    new blocks.  Returns the lists of the s blocks of V and of A V."""
+    (Section 4, algorithm "Modified CA-Arnoldi A-orthonormalization"), or
+    with plain=True by the CA-Arnoldi A-orthonormalization of Section 3.1
+    (algorithm "CA-Arnoldi A-orthonormalization"), which skips the first
+    block's own A-orthonormalization and takes the powers of the raw block.
+    `blocks` holds Q and receives the s new blocks.  Returns the lists of
+    the s blocks of V and of A V."""
     Q, AQ = blocks.all()
     if split:
         Z = split_T(r, dom, t)
@@ -352,14 +355,18 @@ def _ca_arnoldi(Ab, blocks, r, dom, t, s, dtype, orthonormalize, *, split, aimag
     if precond is not None:
         Z = precond(_f64(Z))
     Z = _store(Z, dtype)
-    # W_j: against Q, then against itself
-    Z = cgs2_a(Z, Q, AQ, dtype)
-    W, AW, _ = orthonormalize(Ab, Z, dtype)
+    if plain:
+        # W_j is the raw block (A W_{j-1}, or T(r) at a (re)start)
+        W, AW = Z, None
+    else:
+        # W_j: against Q, then against itself
+        Z = cgs2_a(Z, Q, AQ, dtype)
+        W, AW, _ = orthonormalize(Ab, Z, dtype)
     # the monomial powers of W_j
     powers = [W]
     P = W
     for i in range(1, s):
-        if i == 1 and aimage == "stored":
+        if i == 1 and aimage == "stored" and AW is not None:
             P = AW.copy()
         else:
             P = _spmm(Ab, P, dtype)
@@ -440,7 +447,8 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
     M^{-1} A W_{j-1}; alpha, x and r are updated with V and A V exactly as
     without a preconditioner.
 
-    ca=True builds each iteration's basis with the modified CA-Arnoldi
+    ca=True (or "modified") builds each iteration's basis with the modified
+    CA-Arnoldi
     A-orthonormalization (Section 3.1 with Section 4, algorithm "Modified
     CA-Arnoldi A-orthonormalization"): the CA SRE-CG, CA SRE-CG2 and (with
     variant='msdo') CA MSDO-CG methods.  Per iteration, with Q the blocks
@@ -453,7 +461,11 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
     st-column block (A-CholQR of V, or Pre-CholQR).  READING: A W_j is the
     stored A-image of W_j, A^i W_j (i >= 2) fresh products; with a
     preconditioner every power is M^{-1} A times the previous one (Section
-    5).  The s blocks of V enter Q as s blocks of t columns.
+    5).  The s blocks of V enter Q as s blocks of t columns.  ca="plain"
+    uses the CA-Arnoldi of Section 3.1 instead: W_j is not A-orthonormalized
+    on its own, V = [W_j, A W_j, ..] holds the powers of the raw block.  In
+    the CA forms a breakdown during the first iteration after a (re)start
+    ends the solve (a restart would repeat it).
 
     `trace` (a list, optional) receives one dict per block (the CGS2 output
     Z, A Z, the Gram G, R, W and A W) and one per true-residual check (x
@@ -461,6 +473,8 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
     """
     if s < 1 or t < 1:
         raise ValueError("s and t must be >= 1")
+    if ca not in (False, True, "modified", "plain"):
+        raise ValueError("ca must be False, True / 'modified' or 'plain'")
     if variant not in ("srecg", "srecg2", "msdo"):
         raise ValueError("variant must be 'srecg', 'srecg2' or 'msdo'")
     dtype = np.dtype(basis_dtype).type
@@ -511,7 +525,7 @@ def sstep_srecg(A: sp.csr_matrix, dom: np.ndarray, t: int, s: int, b: np.ndarray
                 if ca:
                     V, AV = _ca_arnoldi(Ab, blocks, r, dom, t, s, dtype, orthonormalize,
                                         split=fresh_start or variant == "msdo",
-                                        aimage=aimage, precond=precond)
+                                        aimage=aimage, precond=precond, plain=ca == "plain")
                     fresh_start = False
                     nblocks += s
                     m_since += s

@@ -78,6 +78,44 @@ def test_ca_poisson_tables(table, variant, t, svals):
         assert _band(got, want), (table, t, s, got, want)
 
 
+@pytest.mark.parametrize("variant,s", [("srecg", 2), ("srecg", 3), ("srecg2", 3)])
+def test_plain_ca_iterates_equal_modified(p30, variant, s):
+    # the CA-Arnoldi of Section 3.1 (powers of the raw block) spans the same
+    # space as the modified one for SRE-CG and SRE-CG2: equal iterates in
+    # exact arithmetic
+    p, A, dom = p30
+    a = O.sstep_srecg(A, dom, 4, s, p.b, tol=1e-8, variant=variant, record=True, ca=True)
+    b = O.sstep_srecg(A, dom, 4, s, p.b, tol=1e-8, variant=variant, record=True, ca="plain")
+    assert a.status == b.status == O.OK
+    assert a.iters == b.iters
+    assert _rel_iterate_gap(a, b, 6) <= 1e-10
+
+
+@pytest.mark.parametrize("t,svals", [(4, (2, 3, 4, 5)), (16, (2, 3, 5))])
+def test_plain_ca_msdo_poisson_table4(t, svals):
+    p = P.poisson2d(rhs="unit", tol=1e-6)
+    A = p.scipy()
+    dom = O.partition_grid(p.shape, PARTS[t])
+    row = pinlib.read_ca_table()[("ca5-msdo", t)]
+    for s in svals:
+        want = row[pinlib.CA_SVALS.index(s)]
+        got = O.sstep_srecg(A, dom, t, s, p.b, tol=1e-6, variant="msdo", ca="plain").iters
+        assert _band(got, want), (t, s, got, want)
+
+
+def test_plain_ca_basis_properties():
+    p = P.poisson2d(40, t=8, parts=(2, 4, 1), seed=12)
+    A = p.scipy()
+    dom = O.partition_grid(p.shape, p.parts)
+    for variant in ("srecg", "msdo"):
+        r = O.sstep_srecg(A, dom, 8, 3, p.b, tol=1e-8, maxit=5, variant=variant, ca="plain",
+                          record=True)
+        assert pinlib.orthonormality_violation(r, A) <= 1e-10
+        assert _whole_basis_violation(r, A) <= 1e-8
+        assert pinlib.petrov_galerkin_violation(r) <= 1e-10
+        assert pinlib.error_drop_violation(r, A, p.xstar) <= 1e-8
+
+
 @pytest.mark.parametrize("variant", ["srecg", "srecg2", "msdo"])
 def test_ca_t1_s1_is_cg(variant):
     p = P.poisson2d(20, t=1, parts=(1, 1, 1), seed=4)
