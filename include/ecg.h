@@ -111,9 +111,13 @@ typedef struct ecg_opts {
                              A-orthonormalized against the kept blocks and
                              itself, then its monomial powers A W, ..,
                              A^{s-1} W are formed and A-orthonormalized
-                             against the kept blocks and each other.  CA
-                             SRE-CG keeps the last s+1 blocks.  0: the s-step
-                             construction (default 0) */
+                             against the kept blocks and each other.
+                             2: the CA-Arnoldi A-orthonormalization of
+                             Section 3.1: the powers of the raw first block,
+                             all A-orthonormalized together.  CA SRE-CG keeps
+                             the last s+1 blocks; a breakdown in the first
+                             iteration after a (re)start ends the solve.
+                             0: the s-step construction (default 0) */
   int32_t reserved[3];    /* must be zero */
 } ecg_opts;
 

@@ -35,6 +35,7 @@ FP64, MIXED = 0, 1
 KCLASSES = ["resid", "tsplit", "cgs_gram", "cgs_update", "spmm", "xr_update", "gram",
             "update", "small", "precond"]
 PREC_NONE, PREC_BJ_IC0 = 0, 1
+CA_NONE, CA_MODIFIED, CA_PLAIN = 0, 1, 2   # opts.ca: s-step, modified / plain CA-Arnoldi
 SPMM_NOALLOC_MAX = 4194304   # n x padded width limit of ecg_spmm_noalloc
 
 
@@ -212,7 +213,7 @@ class Solver:
                  inner_tol: float = 1e-4, max_restarts: int = 20, q_cap_blocks: int = 0,
                  ws_cap_bytes: int = 0, collect_stats: bool = False, grid: int = 0,
                  progress_every: int = 0, permute_domains: bool = True,
-                 ca: bool = False, precond_blocks=None):
+                 ca: int = CA_NONE, precond_blocks=None):
         torch = _torch()
         self._ctx = _P()
         o = _Opts()

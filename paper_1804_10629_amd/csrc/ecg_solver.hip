@@ -390,7 +390,7 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   if (o.device_ptrs != 0 && o.device_ptrs != 1) return fail(ECG_EINVAL, "bad device_ptrs");
   if (o.permute_domains != 0 && o.permute_domains != 1)
     return fail(ECG_EINVAL, "bad permute_domains");
-  if (o.ca != 0 && o.ca != 1) return fail(ECG_EINVAL, "bad ca");
+  if (o.ca < 0 || o.ca > 2) return fail(ECG_EINVAL, "bad ca");
   if (!(o.inner_tol >= 0.0 && o.inner_tol < 1.0)) return fail(ECG_EINVAL, "inner_tol must be in [0, 1)");
   if (o.max_restarts < 0 || o.q_cap_blocks < 0 || o.ws_cap_bytes < 0 || o.grid < 0 ||
       o.progress_every < 0)
@@ -1079,6 +1079,37 @@ struct Engine {
     return ECG_OK;
   }
 
+  // The CA-Arnoldi of Section 3.1 (ca = 2): the raw block W_j (T(r), or
+  // A W_{j-1} = A U_{j-1} R_{j-1}^{-1}) and its raw powers A W_j, ..,
+  // A^{s-1} W_j into slots[0 .. s-1], then each against q and the
+  // iteration's earlier blocks (CGS2) and itself (A-CholQR) -- in exact
+  // arithmetic the CGS2 of all s t columns against q and their A-CholQR.
+  int ca_plain_blocks(int m0, const int* slots, const std::vector<int>& q, int last) {
+    const double bb = c->blk_bytes();
+    const bool prec = c->prec != ECG_PREC_NONE;
+    int rc;
+    if (m0 == 0 || c->o.variant == ECG_MSDO) {
+      Timed tm;
+      c->tstart(tm, ECG_K_TSPLIT, bb + 12.0 * c->n, 0.0);
+      HIP_TRY((launch_tsplit<TPI, S>(c->r, c->dom, U(slots[0]), c->n, c->grid, c->st)));
+      c->tstop(tm);
+    } else if ((rc = scale_into(AU(last), rinv(last), U(slots[0])))) {
+      return rc;
+    }
+    if (prec && (rc = apply_minv(U(slots[0])))) return rc;
+    for (int i = 1; i < c->s; ++i) {
+      if ((rc = power(U(slots[i - 1]), U(slots[i])))) return rc;
+      if (prec && (rc = apply_minv(U(slots[i])))) return rc;
+    }
+    std::vector<int> sl = q;
+    for (int i = 0; i < c->s; ++i) {
+      if (i > 0) sl.push_back(slots[i - 1]);
+      if ((rc = cgs2_slots(sl, U(slots[i]), U(slots[i])))) return rc;
+      if ((rc = cholqr(m0 + 1 + i, slots[i], -1))) return rc;
+    }
+    return ECG_OK;
+  }
+
   // CGS2 of X against the blocks in slots sl into `out` (X and out may be
   // the same block; with no blocks, a copy)
   int cgs2_slots(const std::vector<int>& sl, const S* X, S* out) {
@@ -1117,6 +1148,7 @@ struct Engine {
     const int s = c->s;
     S* Zp = (S*)c->Zp;
     int rc;
+    if (c->o.ca == 2) return ca_plain_blocks(m0, slots, q, last);
     if (m0 == 0 || c->o.variant == ECG_MSDO) {
       S* dst = q.empty() ? U(slots[0]) : Zp;
       Timed tm;
@@ -1302,7 +1334,10 @@ struct Engine {
         }
         if ((rc = read_status(&h))) return rc;
         if (h.breakdown) {       // x, r stay the last completed iterate
-          if (h.breakdown_block >= 2 && restarts < c->o.max_restarts) {
+          // a restart from x would repeat a breakdown in the first block (in
+          // the CA forms: in the first iteration) since the last restart
+          const int first = c->o.ca ? c->s : 1;
+          if (h.breakdown_block > first && restarts < c->o.max_restarts) {
             // a rank-deficient block after the first one since the restart:
             // restart from the last completed iterate
             HIP_TRY(hipMemsetAsync(&c->status->breakdown, 0, 2 * sizeof(int), c->st));

@@ -113,7 +113,7 @@ def test_setup_rejects(small, case):
     elif case == "q_cap":
         kw = {"variant": E.SRECG2, "q_cap_blocks": 1}
     elif case == "ca":
-        kw = {"ca": 2}
+        kw = {"ca": 3}
     code, msg = _setup(n, rp, ci, va, pd, t, s, **kw)
     assert code == E.EINVAL, (case, code, msg)
     assert msg

@@ -198,3 +198,36 @@ def test_ca_bitwise_reproducible(E, poisson):
     assert i1.iters == i2.iters
     assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
     sol.close()
+
+
+@pytest.mark.parametrize("variant,s", [("srecg", 2), ("srecg2", 3), ("msdo", 2), ("msdo", 3)])
+def test_plain_ca_parity(E, poisson, variant, s):
+    # the CA-Arnoldi of Section 3.1 (ca = 2): first iterates and full solve
+    p, A, dom = poisson
+    ref = O.sstep_srecg(A, dom, 8, s, p.b, tol=1e-8, variant=variant, ca="plain", record=True)
+    sol = E.Solver(p.rowptr, p.colind, p.vals, dom, 8, s, variant=_v(E, variant), ca=E.CA_PLAIN)
+    for kmax in (1, 3):
+        x, info = sol.solve(p.b, tol=1e-8, maxit=kmax)
+        assert info.iters == kmax
+        assert _rel(x.cpu().numpy(), ref.extra["xs"][kmax]) <= 1e-9, kmax
+    x, info = sol.solve(p.b, tol=1e-8, maxit=1000)
+    assert ref.status == O.OK and info.status == E.OK
+    assert abs(info.iters - ref.iters) <= 2, (info.iters, ref.iters)
+    assert info.true_relres <= 1e-8
+    assert _rel(x.cpu().numpy(), ref.x) <= 1e-6
+    sol.close()
+
+
+def test_ca_first_iteration_breakdown_ends_the_solve(E, poisson):
+    # b zero on one domain: T(r) has a zero column, the first block breaks
+    # down; in the plain form the zero column reaches the powers too
+    p, A, dom = poisson
+    b = p.b.copy()
+    b[dom == 5] = 0.0
+    for ca, oca in ((E.CA_MODIFIED, True), (E.CA_PLAIN, "plain")):
+        sol = E.Solver(p.rowptr, p.colind, p.vals, dom, 8, 3, ca=ca)
+        x, info = sol.solve(b, tol=1e-8, maxit=100)
+        r = O.sstep_srecg(A, dom, 8, 3, b, tol=1e-8, maxit=100, ca=oca)
+        assert r.status == O.BREAKDOWN and info.status == E.BREAKDOWN
+        assert info.iters == r.iters == 0 and info.restarts == r.restarts == 0
+        sol.close()
