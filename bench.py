@@ -370,7 +370,7 @@ def variant_solves(E, cfgs, maxit, cap=64, only=None):
             rows[name] = {}
             for form, prec in (("fp64", E.FP64), ("mixed", E.MIXED)):
                 log(f"[{cfg} {name} {form}]")
-                _, r = full_solve(E, p, arrs, prec, maxit, form, **kw)
+                _, r = full_solve(E, p, arrs, prec, maxit, form, progress_every=50, **kw)
                 rows[name][form] = r
         out[cfg] = rows
         del arrs
