@@ -37,7 +37,7 @@ __all__ = [
     "csr", "partition_grid", "domain_order", "split_T", "chol_upper", "cgs2_a", "a_cholqr",
     "pre_cholqr", "cg", "srecg", "sstep_srecg", "SolveResult", "basis_matrix", "true_residual",
     "dense_cholesky_solve", "sddmm", "dense_gradient", "Breakdown",
-    "ic0", "block_jacobi_ic0", "apply_llt_inverse", "pcg",
+    "ic0", "block_jacobi_ic0", "block_jacobi_cholesky", "apply_llt_inverse", "pcg",
 ]
 
 OK, MAXIT, BREAKDOWN, STAGNATED = 0, 1, 2, 3
@@ -682,6 +682,27 @@ def block_jacobi_ic0(A: sp.csr_matrix, blocks: np.ndarray) -> sp.csr_matrix:
     keep = blocks[A.row] == blocks[A.col]
     Abd = sp.csr_matrix((A.data[keep], (A.row[keep], A.col[keep])), shape=A.shape)
     return ic0(Abd)
+
+
+def block_jacobi_cholesky(A: sp.csr_matrix, blocks: np.ndarray) -> sp.csr_matrix:
+    """L of the block Jacobi preconditioner M = L L^t whose diagonal blocks
+    A(B_i, B_i) are factorised by complete Cholesky (Section 5, the
+    complete-Cholesky table): per block, the dense Cholesky factor of the
+    block (numpy), placed at the block's rows and columns.  L L^t equals the
+    block-diagonal part of A."""
+    A = sp.csr_matrix(A)
+    blocks = np.asarray(blocks)
+    rows, cols, vals = [], [], []
+    for b in np.unique(blocks):
+        idx = np.flatnonzero(blocks == b)
+        Ab = A[idx][:, idx].toarray()
+        Lb = np.linalg.cholesky(Ab)
+        r, c = np.nonzero(np.tril(Lb))
+        rows.append(idx[r])
+        cols.append(idx[c])
+        vals.append(Lb[r, c])
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=A.shape)
 
 
 def apply_llt_inverse(L: sp.csr_matrix):

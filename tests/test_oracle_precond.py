@@ -180,3 +180,50 @@ def test_breakdown_after_first_block_restarts():
     assert off.status == O.BREAKDOWN and off.iters == 1
     first = O.sstep_srecg(A, dom, 4, 2, p.b, tol=1e-8, precond=zero_column_at(1))
     assert first.status == O.BREAKDOWN and first.iters == 0 and first.restarts == 0
+
+
+# ---------------------------------------------------------------------------
+# Complete Cholesky blocks (Section 5, the complete-Cholesky table)
+# ---------------------------------------------------------------------------
+
+def test_complete_cholesky_reproduces_the_block_diagonal():
+    # L L^t is exactly the block-diagonal part of A (entries between blocks
+    # dropped), and L is lower triangular with a positive diagonal
+    p = P.poisson2d(30, rhs="unit")
+    A = p.scipy()
+    blk = O.partition_grid(p.shape, (3, 2, 1))
+    L = O.block_jacobi_cholesky(A, blk)
+    Ac = sp.coo_matrix(A)
+    keep = blk[Ac.row] == blk[Ac.col]
+    Abd = sp.csr_matrix((Ac.data[keep], (Ac.row[keep], Ac.col[keep])), shape=A.shape).toarray()
+    Ld = L.toarray()
+    assert np.all(np.triu(Ld, 1) == 0) and np.all(np.diag(Ld) > 0)
+    assert np.abs(Ld @ Ld.T - Abd).max() <= 1e-12 * np.abs(Abd).max()
+    # IC(0) is not it (fill-in is dropped there): the pin tells them apart
+    Li = O.block_jacobi_ic0(A, blk).toarray()
+    assert np.abs(Li @ Li.T - Abd).max() > 1e-3
+
+
+def test_complete_cholesky_one_block_is_exact():
+    # one block covering everything: M = A, the first iteration solves
+    p = P.poisson2d(24, rhs="unit")
+    A = p.scipy()
+    dom = O.partition_grid(p.shape, (2, 2, 1))
+    M = O.apply_llt_inverse(O.block_jacobi_cholesky(A, np.zeros(p.n, dtype=np.int32)))
+    r = O.sstep_srecg(A, dom, 4, 2, p.b, tol=1e-10, precond=M)
+    assert r.status == O.OK and r.iters == 1
+
+
+def test_complete_cholesky_poisson2d_counts_in_band():
+    p = P.poisson2d(100, rhs="unit", tol=1e-6)
+    A = p.scipy()
+    M = O.apply_llt_inverse(O.block_jacobi_cholesky(A, O.partition_grid(p.shape, (8, 8, 1))))
+    tab = _table()
+    got_pcg = O.pcg(A, p.b, M, tol=1e-6).iters
+    assert abs(got_pcg - tab[("cpcg", 1)][0]) <= 0.12 * tab[("cpcg", 1)][0]
+    for t, parts in ((2, (2, 1, 1)), (16, (4, 4, 1)), (64, (8, 8, 1))):
+        dom = O.partition_grid(p.shape, parts)
+        for si, s in enumerate((1, 2, 4, 8)):
+            want = tab[("cpsre-cg", t)][si]
+            got = O.sstep_srecg(A, dom, t, s, p.b, tol=1e-6, precond=M).iters
+            assert abs(got - want) <= max(2, 0.10 * want), (t, s, got, want)
