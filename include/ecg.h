@@ -65,7 +65,10 @@ enum ecg_variant   { ECG_SRECG = 0,   /* s-step SRE-CG: each block against the
                                          iteration is T(r_{k-1}) */ };
 enum ecg_orth      { ECG_ACHOLQR = 0, ECG_PRECHOLQR = 1 };
 enum ecg_precond   { ECG_PREC_NONE = 0,   /* no preconditioner */
-                     ECG_PREC_BJ_IC0 = 1  /* block Jacobi, IC(0) blocks (Section 5) */ };
+                     ECG_PREC_BJ_IC0 = 1, /* block Jacobi, IC(0) blocks (Section 5) */
+                     ECG_PREC_BJ_CHOL = 2 /* block Jacobi, complete Cholesky blocks
+                                             (Section 5); the factor's fill grows
+                                             with the blocks: at most 2^28 entries */ };
 enum ecg_precision { ECG_FP64 = 0,    /* everything in binary64 */
                      ECG_MIXED = 1    /* binary32 basis blocks and matrix values
                                          for the basis product; Gram matrices,
@@ -300,13 +303,16 @@ int ecg_get_basis(ecg_ctx* c, double* V, double* AV);
  * Cholesky with zero fill-in (the paper's experiments use 64 blocks, each of
  * the t domains a union of blocks); blocks (n int32 values >= 0, host or
  * device array as the context's other arrays, caller's row order) must
- * place every block inside one domain.  The factorisation runs on the host;
- * the two triangular solves of every application run on the device, level
- * by level.  kind = ECG_PREC_NONE (blocks ignored) removes it.  Applies to
- * every later ecg_solve on the context (all variants and both precision
- * forms).  Errors: ECG_EINVAL (bad kind; NULL blocks; a negative value; a
- * block spanning two domains; an IC(0) pivot <= 0: the matrix is then not
- * suitable for IC(0)), ECG_ENOMEM, ECG_EDEVICE; on error no preconditioner
+ * place every block inside one domain.  kind = ECG_PREC_BJ_CHOL: the same
+ * blocks factorised by complete Cholesky (the fill-in kept; for large 2D or
+ * 3D blocks the factor grows quickly: beyond 2^28 entries ECG_ENOMEM).  The
+ * factorisation runs on the host; the two triangular solves of every
+ * application run on the device, level by level.  kind = ECG_PREC_NONE
+ * (blocks ignored) removes it.  Applies to every later ecg_solve on the
+ * context (all variants, the CA forms and both precision forms).
+ * Errors: ECG_EINVAL (bad kind; NULL blocks; a negative value; a block
+ * spanning two domains; a pivot <= 0: the matrix is then not suitable for
+ * the factorisation), ECG_ENOMEM, ECG_EDEVICE; on error no preconditioner
  * is set.
  */
 int ecg_set_preconditioner(ecg_ctx* c, int32_t kind, const int32_t* blocks);

@@ -34,7 +34,7 @@ ACHOLQR, PRECHOLQR = 0, 1
 FP64, MIXED = 0, 1
 KCLASSES = ["resid", "tsplit", "cgs_gram", "cgs_update", "spmm", "xr_update", "gram",
             "update", "small", "precond"]
-PREC_NONE, PREC_BJ_IC0 = 0, 1
+PREC_NONE, PREC_BJ_IC0, PREC_BJ_CHOL = 0, 1, 2
 CA_NONE, CA_MODIFIED, CA_PLAIN = 0, 1, 2   # opts.ca: s-step, modified / plain CA-Arnoldi
 SPMM_NOALLOC_MAX = 4194304   # n x padded width limit of ecg_spmm_noalloc
 

@@ -28,6 +28,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <queue>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1755,7 +1756,8 @@ void bucket_levels(const std::vector<int>& level, std::vector<int32_t>& out, std
 
 extern "C" int ecg_set_preconditioner(ecg_ctx* c, int32_t kind, const int32_t* blocks) {
   if (!c) return fail(ECG_EINVAL, "NULL context");
-  if (kind != ECG_PREC_NONE && kind != ECG_PREC_BJ_IC0) return fail(ECG_EINVAL, "bad kind");
+  if (kind != ECG_PREC_NONE && kind != ECG_PREC_BJ_IC0 && kind != ECG_PREC_BJ_CHOL)
+    return fail(ECG_EINVAL, "bad kind");
   free_prec(c);
   if (kind == ECG_PREC_NONE) return ECG_OK;
   if (!blocks) return fail(ECG_EINVAL, "blocks is NULL");
@@ -1794,16 +1796,68 @@ extern "C" int ecg_set_preconditioner(ecg_ctx* c, int32_t kind, const int32_t* b
       return fail(ECG_EINVAL, "preconditioner block " + std::to_string(bl[i]) +
                                   " spans more than one domain");
   }
-  // IC(0) of the block diagonal part, row by row in the solver's order:
-  // L_ij = (A_ij - sum_{k<j} L_ik L_jk) / L_jj over the pattern, L_ii =
-  // sqrt(A_ii - sum L_ik^2)
   std::vector<int64_t> lp(n + 1, 0);
   std::vector<int32_t> lc;
   std::vector<double> lv, diag(n);
   lc.reserve((size_t)(nnz - n) / 2 + 16);
   lv.reserve((size_t)(nnz - n) / 2 + 16);
   std::vector<std::pair<int32_t, double>> row;
-  for (int64_t i = 0; i < n; ++i) {
+  if (kind == ECG_PREC_BJ_CHOL) {
+    // complete Cholesky of the block diagonal part, row by row in the
+    // solver's order (up-looking): row i of L solves L(0:i-1, 0:i-1) l =
+    // A(0:i-1, i) over i's block by a sparse forward substitution; a
+    // nonzero l_j spreads to the rows p of column j computed so far, which
+    // is where the fill comes from
+    constexpr int64_t kMaxFactor = int64_t(1) << 28;   // entries of L
+    std::vector<std::vector<std::pair<int32_t, double>>> colL(n);
+    std::vector<double> xa(n, 0.0);
+    std::vector<int64_t> mark(n, -1);
+    std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>> heap;
+    for (int64_t i = 0; i < n; ++i) {
+      double aii = 0.0;
+      for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const int32_t j = ci[e];
+        if (j == i) {
+          aii += av[e];
+        } else if (j < i && bl[j] == bl[i]) {
+          xa[j] += av[e];
+          if (mark[j] != i) {
+            mark[j] = i;
+            heap.push(j);
+          }
+        }
+      }
+      double d = aii;
+      while (!heap.empty()) {
+        const int32_t j = heap.top();
+        heap.pop();
+        const double lij = xa[j] / diag[j];
+        xa[j] = 0.0;
+        lc.push_back(j);
+        lv.push_back(lij);
+        d -= lij * lij;
+        for (const auto& pl : colL[j]) {
+          xa[pl.first] -= pl.second * lij;
+          if (mark[pl.first] != i) {
+            mark[pl.first] = i;
+            heap.push(pl.first);
+          }
+        }
+      }
+      if (!(d > 0.0) || !std::isfinite(d))
+        return fail(ECG_EINVAL, "Cholesky pivot of row " + std::to_string(i) + " is not positive");
+      diag[i] = std::sqrt(d);
+      for (int64_t a = lp[i]; a < (int64_t)lc.size(); ++a) colL[lc[a]].emplace_back((int32_t)i, lv[a]);
+      lp[i + 1] = (int64_t)lc.size();
+      if ((int64_t)lc.size() > kMaxFactor)
+        return fail(ECG_ENOMEM, "complete Cholesky factor beyond " + std::to_string(kMaxFactor) +
+                                    " entries (blocks too large)");
+    }
+  }
+  // IC(0) of the block diagonal part, row by row in the solver's order:
+  // L_ij = (A_ij - sum_{k<j} L_ik L_jk) / L_jj over the pattern, L_ii =
+  // sqrt(A_ii - sum L_ik^2)
+  for (int64_t i = 0; kind == ECG_PREC_BJ_IC0 && i < n; ++i) {
     row.clear();
     double aii = 0.0;
     for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {

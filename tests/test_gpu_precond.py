@@ -105,3 +105,62 @@ def test_preconditioner_rejects_blocks_across_domains(E):
     _, info = sol.solve(p.b, tol=1e-8, maxit=500)
     assert info.status == E.OK
     sol.close()
+
+
+# complete Cholesky blocks (Section 5, the complete-Cholesky table)
+
+@pytest.mark.parametrize("m,t,s,parts,bparts,variant", [
+    (100, 8, 2, (2, 4, 1), (8, 8, 1), "srecg"),
+    (100, 8, 4, (2, 4, 1), (8, 8, 1), "srecg2"),
+    (60, 16, 3, (4, 4, 1), (4, 4, 1), "msdo"),
+    (64, 64, 2, (8, 8, 1), (8, 8, 1), "srecg")])
+def test_complete_cholesky_parity(E, m, t, s, parts, bparts, variant):
+    p = P.poisson2d(m, t=t, parts=parts)
+    A = p.scipy()
+    dom = O.partition_grid(p.shape, parts)
+    blk = O.partition_grid(p.shape, bparts)
+    M = O.apply_llt_inverse(O.block_jacobi_cholesky(A, blk))
+    vmap = {"srecg": E.SRECG, "srecg2": E.SRECG2, "msdo": E.MSDO}
+    sol = E.Solver(p.rowptr, p.colind, p.vals, dom, t, s, variant=vmap[variant])
+    sol.set_preconditioner(E.PREC_BJ_CHOL, blk)
+    ref = O.sstep_srecg(A, dom, t, s, p.b, tol=1e-8, maxit=500, variant=variant, precond=M,
+                        record=True)
+    x, info = sol.solve(p.b, tol=1e-8, maxit=500)
+    assert info.status == E.OK and info.true_relres <= 1e-8
+    assert abs(info.iters - ref.iters) <= 2, (info.iters, ref.iters)
+    assert _rel(x.cpu().numpy(), ref.x) <= 1e-6
+    x1, _ = sol.solve(p.b, tol=1e-8, maxit=1)
+    assert _rel(x1.cpu().numpy(), ref.extra["xs"][1]) <= 1e-10
+    sol.close()
+
+
+def test_complete_cholesky_one_domain_is_exact(E):
+    # t = 1 and one block: M = A, so the first iteration solves the system
+    p = P.poisson2d(30, t=1, parts=(1, 1, 1))
+    dom = np.zeros(p.n, dtype=np.int32)
+    sol = E.Solver(p.rowptr, p.colind, p.vals, dom, 1, 2)
+    sol.set_preconditioner(E.PREC_BJ_CHOL, dom)
+    x, info = sol.solve(p.b, tol=1e-10, maxit=10)
+    assert info.status == E.OK and info.iters == 1
+    assert np.linalg.norm(x.cpu().numpy() - p.xstar) <= 1e-9 * np.linalg.norm(p.xstar)
+    sol.close()
+
+
+def test_complete_cholesky_3d_and_ca(E):
+    # a 3D skyscraper field with 8 blocks in 4 domains, s-step and CA SRE-CG
+    shape = (16, 16, 16)
+    p = P.make_problem("sky", shape, P.kappa_skyscraper(shape, 2, tile=4), seed=2, t=4, s=2,
+                       parts=(2, 2, 1))
+    A = p.scipy()
+    dom = O.partition_grid(shape, (2, 2, 1))
+    blk = O.partition_grid(shape, (2, 2, 2))
+    M = O.apply_llt_inverse(O.block_jacobi_cholesky(A, blk))
+    for ca in (False, True):
+        ref = O.sstep_srecg(A, dom, 4, 2, p.b, tol=1e-8, maxit=500, precond=M, ca=ca)
+        sol = E.Solver(p.rowptr, p.colind, p.vals, dom, 4, 2, ca=int(ca))
+        sol.set_preconditioner(E.PREC_BJ_CHOL, blk)
+        x, info = sol.solve(p.b, tol=1e-8, maxit=500)
+        assert info.status == E.OK and info.true_relres <= 1e-8
+        assert abs(info.iters - ref.iters) <= 2, (ca, info.iters, ref.iters)
+        assert _rel(x.cpu().numpy(), ref.x) <= 1e-6
+        sol.close()
