@@ -33,7 +33,7 @@ def test_msdo_poisson_table4(t):
     A = p.scipy()
     dom = O.partition_grid(p.shape, PARTS[t])
     _, row = pinlib.read_msdo_table()[t]
-    for s in (1, 2, 5):
+    for s in ((1, 2, 5) if t <= 4 else (2, 5)):
         want = row[pinlib.MSDO_SVALS.index(s)]
         got = O.sstep_srecg(A, dom, t, s, p.b, tol=1e-6, variant="msdo").iters
         assert _band(got, want), (t, s, got, want)
