@@ -1258,7 +1258,6 @@ struct Engine {
     const bool cg2 = c->o.variant != ECG_SRECG;   // every block since the restart is kept
     int slot_of[3] = {-1, -1, -1};   // slots of blocks m, m-1, m-2
     std::vector<int> since;          // CA forms: slots of the blocks since the restart
-    bool have_basis = false;
     while (true) {
       const double thr = std::max(inner * rho_restart, thr_final);
       while (rho > thr && k < maxit) {
@@ -1366,7 +1365,6 @@ struct Engine {
           progress("", k, restarts, rho);
         c->last_nb = c->s;
         for (int i = 0; i < c->s; ++i) c->last_slots[i] = slots[i];
-        have_basis = true;
       }
       if (status == ECG_BREAKDOWN) break;
       if (rho > thr) {
@@ -1395,7 +1393,6 @@ struct Engine {
       slot_of[0] = slot_of[1] = slot_of[2] = -1;
       since.clear();
     }
-    (void)have_basis;
     // final true residual (the residual kernel leaves r = b - A x)
     if ((rc = resid(1))) return rc;
     if ((rc = read_status(&h))) return rc;
