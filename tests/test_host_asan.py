@@ -1,4 +1,5 @@
-"""The library's host code under AddressSanitizer, on the CPU.
+"""The library's host code under AddressSanitizer and UndefinedBehavior-
+Sanitizer, on the CPU.
 
 ecg_solver.hip is compiled with the sanitizer on its host side only (the
 device code is not instrumented) and linked with the kernels object of the
@@ -21,7 +22,9 @@ HIPCC = "/opt/rocm/bin/hipcc"
 CLANG = "/opt/rocm/llvm/bin/clang++"
 FLAGS = ["--offload-arch=gfx950", "-std=c++17", "-fPIC", "-O1", "-g",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer",
+         "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+         "-Xarch_host", "-fno-sanitize-recover=undefined",
+         "-Xarch_host", "-fno-omit-frame-pointer",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
@@ -37,7 +40,7 @@ def _run(cmd, **kw):
 
 
 def _link(objs, out):
-    r = _run([CLANG, *objs, "-fsanitize=address", "-L/opt/rocm/lib", "-lamdhip64",
+    r = _run([CLANG, *objs, "-fsanitize=address,undefined", "-L/opt/rocm/lib", "-lamdhip64",
               "-Wl,-rpath,/opt/rocm/lib", "-o", out])
     assert r.returncode == 0, r.stderr[-2000:]
 
@@ -75,4 +78,4 @@ def test_setup_host_code_is_clean_under_asan(tmp_path):
     _link([dobj, sobj, KOBJ], exe)
     r = _run([exe], env=_env())
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), (r.stdout, r.stderr[-3000:])
-    assert "AddressSanitizer" not in r.stderr
+    assert "AddressSanitizer" not in r.stderr and "runtime error" not in r.stderr
