@@ -6,6 +6,8 @@ benchmark uses (default grid, stream and options).
   oracle's (x_1 over all 2.1M rows; at 16 columns also the basis it built),
   in the FP64 and the mixed form.
 * 128^3 anisotropic, CA SRE-CG: the first two iterates against the oracle.
+* 1000^2 log-uniform (t = 16, s = 3): x_1 and x_4 over all 1M rows and the
+  residual history against the oracle's.
 * 128^3 skyscraper: a full solve, its true residual recomputed on the CPU,
   and two 60-iteration solves in each form that agree bit for bit.
 * 256^3 random blocks (t = 64, s = 2, 16.8M rows): too large for the oracle;
@@ -131,6 +133,29 @@ def test_anisotropic_first_iteration(E, mixed):
     rel = np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr)
     print(f"x_1 relative difference {rel:.2e}")
     assert rel <= (1e-6 if mixed else 1e-10)
+    sol.close()
+
+
+def test_log_uniform_first_iterations(E):
+    # 1000^2 log-uniform (t = 16, s = 3): the full solve is rounding-sensitive
+    # (its count moves with ulp-level changes), the first iterates are not
+    # (perturbing b by one part in 1e15 moves the oracle's x_4 by 7e-15), so
+    # x_1 and x_4 over all 1M rows and the residual history are compared with
+    # the oracle's
+    p = P.CONFIGS["C4"]()
+    A = p.scipy()
+    dom = O.partition_grid(p.shape, p.parts)
+    ref = O.sstep_srecg(A, dom, p.t, p.s, p.b, tol=p.tol, maxit=4, record=True)
+    sol, _ = _device_solver(E, p)
+    for k in (1, 4):
+        x, info = sol.solve(p.b, tol=p.tol, maxit=k)
+        assert info.iters == k
+        xr = ref.extra["xs"][k]
+        rel = float(np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr))
+        h_gpu, h_or = np.asarray(info.hist[:k + 1]), np.asarray(ref.hist[:k + 1])
+        hrel = float(np.max(np.abs(h_gpu - h_or) / h_or))
+        print(f"log-uniform 1000^2 x_{k}: rel {rel:.2e}, history {hrel:.2e}")
+        assert rel <= 1e-9 and hrel <= 1e-9
     sol.close()
 
 
