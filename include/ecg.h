@@ -260,14 +260,19 @@ int ecg_sddmm(ecg_ctx* c, const double* lambda, const double* x, double* grad_va
 int ecg_spmm(ecg_ctx* c, const double* X, double* Y, int32_t k);
 
 /*
- * ecg_spmm for callers that cannot allocate device memory (code under HIP
- * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * ecg_spmm for callers that cannot allocate device memory (serving loops,
+ * harnesses that forbid hipMalloc, code around a HIP graph capture): the same
  * kernels and result, but the two staging blocks (X packed to the padded
  * width w = 16, 32 or 64 for k <= 16, <= 32, <= 64, in the solver's row
  * order, and its product) live in a fixed 64 MiB device array of the
  * library, one per GPU, held until the process ends.  The call makes no
  * hipMalloc / hipFree and allocates nothing else on the device; X and Y are
- * host or device pointers as opts.device_ptrs says, exactly as for ecg_spmm.
+ * host or device pointers as opts.device_ptrs says, exactly as for ecg_spmm
+ * (host arrays are copied with hipMemcpyAsync, which stages pageable memory
+ * through the HIP runtime's own buffers: a caller that must avoid even that
+ * passes device pointers).  Like every call here it returns after its work
+ * on opts.hip_stream has completed, so it is not itself recorded into a
+ * graph: it synchronizes that stream.
  * Limit: n * w <= ECG_SPMM_NOALLOC_MAX (both staging blocks fit the array);
  * larger inputs return ECG_EINVAL before any work.  Every call on a GPU uses
  * that GPU's one array, and each call writes all of it that it reads, so
