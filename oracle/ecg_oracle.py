@@ -80,13 +80,19 @@ def partition_grid(shape, parts) -> np.ndarray:
     return dom
 
 
-def domain_order(dom: np.ndarray) -> np.ndarray:
+def domain_order(dom: np.ndarray, key: np.ndarray | None = None) -> np.ndarray:
     """Domain-contiguous row order: the rows of domain 0 in increasing index
     order, then those of domain 1, and so on (Section 4 reorders the matrix
     by its Metis domains; READING: rows keep the caller's order within a
-    domain).  order[i] is the original row placed at position i.  Parity:
-    bit-exact (integers)."""
-    return np.argsort(np.asarray(dom), kind="stable").astype(np.int32)
+    domain, or, when a per-row key is given, are sorted by key within a
+    domain with ties in index order -- the paper leaves the order inside a
+    domain open).  order[i] is the original row placed at position i.
+    Parity: bit-exact (integers)."""
+    dom = np.asarray(dom)
+    if key is None:
+        return np.argsort(dom, kind="stable").astype(np.int32)
+    idx = np.arange(dom.shape[0])
+    return np.lexsort((idx, np.asarray(key), dom)).astype(np.int32)
 
 
 def split_T(r: np.ndarray, dom: np.ndarray, t: int) -> np.ndarray:

@@ -501,6 +501,12 @@ def test_domain_order_brute_force():
         want = sorted(range(n), key=lambda i: (int(dom[i]), i))
         got = O.domain_order(dom)
         assert got.dtype == np.int32 and got.tolist() == want
+    # with keys (small range, so that ties occur): sort by (domain, key, row)
+    for n, t in ((1, 1), (17, 3), (300, 8)):
+        dom = rng.integers(0, t, n).astype(np.int32)
+        key = rng.integers(-5, 5, n).astype(np.int64)
+        want = sorted(range(n), key=lambda i: (int(dom[i]), int(key[i]), i))
+        assert O.domain_order(dom, key).tolist() == want
     p = P.poisson2d(12, t=8, parts=(2, 4, 1))
     dom = O.partition_grid(p.shape, p.parts)
     order = O.domain_order(dom)
