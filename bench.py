@@ -91,10 +91,11 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kclass, workload, form="fp64"):
+def measured_traffic(kclass, workload, form="fp64", row_order="domain"):
     """HBM bytes per launch of a kernel class from a committed rocprofv3
     --pmc summary (FETCH_SIZE and WRITE_SIZE, scaled against a plain copy),
-    or None when no summary matches this workload, form and kernel source."""
+    or None when no summary matches this workload, form, row order and
+    kernel source."""
     src = kernel_source_hash()
     if not os.path.isdir(PROFILES):
         return None
@@ -109,12 +110,13 @@ def measured_traffic(kclass, workload, form="fp64"):
                 d = json.loads(m.group(1))
                 if (d.get("kclass") == kclass and d.get("workload") == workload
                         and d.get("form", "fp64") == form
+                        and d.get("row_order", "domain") == row_order
                         and d.get("kernel_source_sha256_16") == src):
                     return d
     return None
 
 
-def roofline(ktab, workload, form):
+def roofline(ktab, workload, form, row_order="domain"):
     """The dominant kernel class (device time) against its binding peak:
     FP64 matrix cores when its flops at 78.6 TFLOP/s take longer than its
     bytes at 8 TB/s, HBM otherwise."""
@@ -123,7 +125,7 @@ def roofline(ktab, workload, form):
     sec = k["us_per_launch"] * 1e-6
     t_mem = k["gb_per_launch"] / PEAK_HBM_GBS
     t_mfma = k["gflop_per_launch"] / (PEAK_F64_MFMA_TFS * 1e3)
-    tr = measured_traffic(name, workload, form)
+    tr = measured_traffic(name, workload, form, row_order)
     common = {"kernel": name, "algorithmic_gb_per_launch": k["gb_per_launch"],
               "gflop_per_launch": k["gflop_per_launch"],
               "traffic": tr["hbm_gb_per_launch"] if tr else None,
@@ -256,13 +258,14 @@ def device_arrays(E, p):
     return rp, ci, va, dom, bd
 
 
-def iteration_form(E, p, arrs, precision, steps, warmup, form):
+def iteration_form(E, p, arrs, precision, steps, warmup, form, **opts):
     """W untimed and K timed s-step iterations, then a separate K-iteration
-    solve with per-kernel events for the kernel table."""
+    solve with per-kernel events for the kernel table (`opts`: further
+    Solver options, e.g. the row order)."""
     import torch
     rp, ci, va, dom, bd = arrs
     t0 = time.perf_counter()
-    sol = E.Solver(rp, ci, va, dom, p.t, p.s, precision=precision)
+    sol = E.Solver(rp, ci, va, dom, p.t, p.s, precision=precision, **opts)
     torch.cuda.synchronize()
     log(f"[{form}] setup {time.perf_counter() - t0:.1f} s")
     if warmup > 0:
@@ -276,7 +279,7 @@ def iteration_form(E, p, arrs, precision, steps, warmup, form):
     log(f"[{form}] timed: {info.iters} iterations in {wall * 1e3:.1f} ms, "
         f"rho/rho0 {info.relres:.2e}")
     sol.close()
-    st = E.Solver(rp, ci, va, dom, p.t, p.s, precision=precision, collect_stats=True)
+    st = E.Solver(rp, ci, va, dom, p.t, p.s, precision=precision, collect_stats=True, **opts)
     _, si = st.solve(bd, tol=p.tol, maxit=steps)
     stats = st.stats()
     st.close()
@@ -309,13 +312,13 @@ def full_solve(E, p, arrs, precision, maxit, form, progress_every=0, **opts):
                 "rel_err_vs_xstar": float(np.linalg.norm(xs - p.xstar) / np.linalg.norm(p.xstar))}
 
 
-def precond_solve(E, p, arrs, precision, maxit, form):
+def precond_solve(E, p, arrs, precision, maxit, form, **opts):
     """Time-to-tolerance of the split preconditioned s-step SRE-CG with the
     block Jacobi IC(0) preconditioner whose blocks are the t domains; the
     host factorisation is timed separately."""
     import torch
     rp, ci, va, dom, bd = arrs
-    sol = E.Solver(rp, ci, va, dom, p.t, p.s, precision=precision)
+    sol = E.Solver(rp, ci, va, dom, p.t, p.s, precision=precision, **opts)
     t0 = time.perf_counter()
     sol.set_preconditioner(E.PREC_BJ_IC0, dom)
     torch.cuda.synchronize()
@@ -421,6 +424,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the full 128^3 skyscraper solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--row-order", choices=("domain", "morton"), default="domain",
+                    help="rows of each domain in the caller's order or in Morton order")
     ap.add_argument("--calibrate", action="store_true",
                     help="time a plain 256 MiB device copy (the reference for HBM counters)")
     args = ap.parse_args()
@@ -457,17 +462,18 @@ def main():
         return
 
     arrs = device_arrays(E, p)
-    main_f = iteration_form(E, p, arrs, E.FP64, args.steps, args.warmup, "fp64")
+    ro = {"row_key": E.grid_morton_keys(p.shape)} if args.row_order == "morton" else {}
+    main_f = iteration_form(E, p, arrs, E.FP64, args.steps, args.warmup, "fp64", **ro)
     mixed = None
     if not args.no_mixed:
-        mixed = iteration_form(E, p, arrs, E.MIXED, args.steps, args.warmup, "mixed")
+        mixed = iteration_form(E, p, arrs, E.MIXED, args.steps, args.warmup, "mixed", **ro)
     prec = None
     if not args.no_solve:
         prec = {"preconditioner": "block Jacobi, IC(0) blocks = the t domains (Section 5)",
                 "workload": describe(p),
-                "fp64": precond_solve(E, p, arrs, E.FP64, args.maxit, "fp64")}
+                "fp64": precond_solve(E, p, arrs, E.FP64, args.maxit, "fp64", **ro)}
         if not args.no_mixed:
-            prec["mixed"] = precond_solve(E, p, arrs, E.MIXED, args.maxit, "mixed")
+            prec["mixed"] = precond_solve(E, p, arrs, E.MIXED, args.maxit, "mixed", **ro)
             prec["mixed"]["speedup_vs_fp64"] = round(prec["fp64"]["time_s"] / prec["mixed"]["time_s"], 3)
     del arrs
     torch.cuda.empty_cache()
@@ -501,19 +507,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": describe(p), "n": p.n, "nnz": p.nnz, "t": p.t, "s": p.s,
                    "tol": p.tol, "variant": "s-step SRE-CG", "parallelism": "single GPU",
-                   "step": "one s-step iteration"},
+                   "step": "one s-step iteration", "row_order": args.row_order},
         "value_definition": ("algorithmic HBM bytes of the kernels of the timed s-step "
                              "iterations over their wall time (binary64)"),
         "gb_per_step": round(bytes_per_iter / 1e9, 3),
         "kernels": main_f["kernels"],
-        "roofline": roofline(main_f["kernels"], p.name, "fp64"),
+        "roofline": roofline(main_f["kernels"], p.name, "fp64", args.row_order),
         "mixed": None if mixed is None else {
             "value": round(mixed["gbs"], 1), "unit": "GB/s",
             "ms_per_step": round(mixed["ms_per_step"], 3),
             "speedup_per_step_vs_fp64": round(main_f["ms_per_step"] / mixed["ms_per_step"], 3),
             "gb_per_step": round(mixed["bytes"] / max(mixed["iters"], 1) / 1e9, 3),
             "kernels": mixed["kernels"],
-            "roofline": roofline(mixed["kernels"], p.name, "mixed"),
+            "roofline": roofline(mixed["kernels"], p.name, "mixed", args.row_order),
         },
         "time_to_1e8": {"unpreconditioned": ("python bench.py --full --form fp64|mixed; "
                                              "profiles/randomblocks3d_256_time_to_1e8.md"),

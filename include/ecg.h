@@ -121,7 +121,17 @@ typedef struct ecg_opts {
                              the last s+1 blocks; a breakdown in the first
                              iteration after a (re)start ends the solve.
                              0: the s-step construction (default 0) */
-  int32_t reserved[3];    /* must be zero */
+  int32_t reserved[1];    /* must be zero */
+  const int64_t* row_key; /* with permute_domains = 1: n keys (host or device
+                             array as the other arrays of ecg_setup); the
+                             rows of each domain are then stored by ascending
+                             key (ties in the caller's order) instead of in
+                             the caller's order.  A locality order (for grid
+                             problems the Morton order, ecg_grid_morton_keys)
+                             keeps the rows a sparse row reaches close in
+                             device memory, so that the basis product finds
+                             them in L2.  NULL: the caller's order within a
+                             domain (default NULL) */
 } ecg_opts;
 
 /* Fill *o with the defaults above. */
@@ -186,6 +196,16 @@ typedef struct ecg_ctx ecg_ctx;
  */
 int ecg_partition_grid(int64_t nx, int64_t ny, int64_t nz, int32_t px, int32_t py,
                        int32_t pz, int32_t* dom_dev, void* stream);
+
+/*
+ * Morton (Z-order) keys of an nx x ny x nz grid, rows numbered as for
+ * ecg_partition_grid: keys[i] interleaves the bits of the cell's
+ * coordinates (bit b of x, y, z at bits 3b, 3b+1, 3b+2).  A row order for
+ * ecg_opts.row_key.  keys: host array of nx*ny*nz int64, written on the
+ * host.  Errors: ECG_EINVAL (non-positive sizes, nx*ny*nz >= 2^31, a side
+ * >= 2^21, NULL pointer).
+ */
+int ecg_grid_morton_keys(int64_t nx, int64_t ny, int64_t nz, int64_t* keys);
 
 /*
  * Create a solver for the n x n SPD matrix (rowptr, colind, vals) with the
@@ -325,8 +345,9 @@ int ecg_set_preconditioner(ecg_ctx* c, int32_t kind, const int32_t* blocks);
 /*
  * The solver's row order: order[i] (n int32 values, host or device array as
  * the context's other arrays) is the caller's row that the solver stores as
- * row i -- the rows of domain 0 in the caller's order, then those of domain
- * 1, and so on (opts.permute_domains = 1), or i itself (0).
+ * row i -- the rows of domain 0 in the caller's order (by ascending
+ * opts.row_key when given), then those of domain 1, and so on
+ * (opts.permute_domains = 1), or i itself (0).
  * Errors: ECG_EINVAL (NULL argument), ECG_EDEVICE.
  */
 int ecg_domain_order(ecg_ctx* c, int32_t* order);

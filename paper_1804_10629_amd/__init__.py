@@ -54,7 +54,7 @@ class _Opts(ctypes.Structure):
         ("hip_stream", ctypes.c_void_p), ("collect_stats", ctypes.c_int32),
         ("grid", ctypes.c_int32), ("progress_every", ctypes.c_int32),
         ("permute_domains", ctypes.c_int32), ("ca", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("reserved", ctypes.c_int32 * 1), ("row_key", ctypes.c_void_p),
     ]
 
 
@@ -84,6 +84,7 @@ _SIGS = {
     "ecg_kclass_name": (ctypes.c_char_p, [ctypes.c_int]),
     "ecg_partition_grid": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "ecg_grid_morton_keys": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _P]),
     "ecg_setup": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int64, _P, _P, _P, _P,
                                  ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_Opts)]),
     "ecg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int32, _P, _P, _P,
@@ -182,6 +183,14 @@ def partition_grid(shape: Sequence[int], parts: Sequence[int]):
     return dom
 
 
+def grid_morton_keys(shape: Sequence[int]) -> np.ndarray:
+    """Morton keys of a grid's cells (host int64 array), for Solver(row_key=)."""
+    nx, ny, nz = (int(v) for v in shape)
+    keys = np.empty(nx * ny * nz, dtype=np.int64)
+    _check(lib.ecg_grid_morton_keys(nx, ny, nz, keys.ctypes.data))
+    return keys
+
+
 @dataclass
 class SolveInfo:
     status: int
@@ -206,6 +215,8 @@ class Solver:
     rowptr/colind/vals: CSR (int32, int32, float64), numpy arrays or torch
     tensors; partition: int32 domain index per row in [0, t).  Inputs are
     copied to the device by the library (as CUDA tensors, device_ptrs=1).
+    row_key: optional int64 per row; the rows of each domain are then stored
+    by ascending key (grid_morton_keys gives the Morton order of a grid).
     """
 
     def __init__(self, rowptr, colind, vals, partition, t: int, s: int, *,
@@ -213,7 +224,7 @@ class Solver:
                  inner_tol: float = 1e-4, max_restarts: int = 20, q_cap_blocks: int = 0,
                  ws_cap_bytes: int = 0, collect_stats: bool = False, grid: int = 0,
                  progress_every: int = 0, permute_domains: bool = True,
-                 ca: int = CA_NONE, precond_blocks=None):
+                 ca: int = CA_NONE, precond_blocks=None, row_key=None):
         torch = _torch()
         self._ctx = _P()
         o = _Opts()
@@ -231,6 +242,8 @@ class Solver:
         ci = _dev_tensor(colind, torch.int32)
         va = _dev_tensor(vals, torch.float64)
         pd = _dev_tensor(partition, torch.int32)
+        rk = _dev_tensor(row_key, torch.int64) if row_key is not None else None
+        o.row_key = rk.data_ptr() if rk is not None else None
         self.n = int(rp.numel() - 1)
         self.nnz = int(ci.numel())
         self.t, self.s = int(t), int(s)

@@ -346,6 +346,30 @@ extern "C" int ecg_partition_grid(int64_t nx, int64_t ny, int64_t nz, int32_t px
   return ECG_OK;
 }
 
+extern "C" int ecg_grid_morton_keys(int64_t nx, int64_t ny, int64_t nz, int64_t* keys) {
+  if (!keys) return fail(ECG_EINVAL, "keys is NULL");
+  if (nx <= 0 || ny <= 0 || nz <= 0) return fail(ECG_EINVAL, "grid sizes must be positive");
+  constexpr int64_t kSide = int64_t(1) << 21;   // 3 x 21 bits fit an int64 key
+  if (nx >= kSide || ny >= kSide || nz >= kSide) return fail(ECG_EINVAL, "grid side >= 2^21");
+  if (nx * ny >= (int64_t(1) << 31) || nx * ny * nz >= (int64_t(1) << 31))
+    return fail(ECG_EINVAL, "grid too large for int32 row indices");
+  // spread the 21 low bits of v to every third bit
+  auto spread = [](uint64_t v) {
+    uint64_t r = 0;
+    for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1u) << (3 * b);
+    return r;
+  };
+  for (int64_t k = 0; k < nz; ++k) {
+    const uint64_t kz = spread((uint64_t)k) << 2;
+    for (int64_t j = 0; j < ny; ++j) {
+      const uint64_t kyz = kz | (spread((uint64_t)j) << 1);
+      int64_t* row = keys + nx * (j + ny * k);
+      for (int64_t i = 0; i < nx; ++i) row[i] = (int64_t)(kyz | spread((uint64_t)i));
+    }
+  }
+  return ECG_OK;
+}
+
 // Allocate and zero block pairs up to `want` slots (padding columns of a
 // block stay zero from here on).  On failure the slots allocated so far
 // stay usable and ECG_ENOMEM is returned.
@@ -376,8 +400,7 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   ecg_opts o;
   if (opts) o = *opts;
   else ecg_opts_default(&o);
-  for (int i = 0; i < 3; ++i)
-    if (o.reserved[i] != 0) return fail(ECG_EINVAL, "reserved option fields must be zero");
+  if (o.reserved[0] != 0) return fail(ECG_EINVAL, "reserved option fields must be zero");
   if (!rowptr || !colind || !vals || !partition) return fail(ECG_EINVAL, "NULL array argument");
   if (n <= 0) return fail(ECG_EINVAL, "n must be positive");
   if (n >= (int64_t(1) << 31)) return fail(ECG_EINVAL, "n must be < 2^31");
@@ -392,6 +415,8 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
   if (o.permute_domains != 0 && o.permute_domains != 1)
     return fail(ECG_EINVAL, "bad permute_domains");
   if (o.ca < 0 || o.ca > 2) return fail(ECG_EINVAL, "bad ca");
+  if (o.row_key && o.permute_domains != 1)
+    return fail(ECG_EINVAL, "row_key needs permute_domains = 1");
   if (!(o.inner_tol >= 0.0 && o.inner_tol < 1.0)) return fail(ECG_EINVAL, "inner_tol must be in [0, 1)");
   if (o.max_restarts < 0 || o.q_cap_blocks < 0 || o.ws_cap_bytes < 0 || o.grid < 0 ||
       o.progress_every < 0)
@@ -436,8 +461,9 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
 
   // Domain-contiguous order (the paper reorders the matrix by its Metis
   // domains, Section 4): solver row i is the caller's row perm[i], rows
-  // sorted by domain, keeping the caller's order within a domain; column
-  // indices renumbered and sorted ascending within each row.
+  // sorted by domain, keeping the caller's order within a domain (or, with
+  // row_key, sorted by key within a domain, ties in the caller's order);
+  // column indices renumbered and sorted ascending within each row.
   const bool permute = o.permute_domains == 1;
   std::vector<int32_t> perm_h, emap_h, prp_h, pci_h, pdom_h;
   std::vector<double> pv_h;
@@ -447,6 +473,15 @@ extern "C" int ecg_setup(ecg_ctx** out, int64_t n, const int32_t* rowptr, const 
     perm_h.resize(n);
     std::vector<int32_t> iperm(n);
     for (int64_t i = 0; i < n; ++i) perm_h[pos[pd[i]]++] = (int32_t)i;
+    if (o.row_key) {
+      std::vector<int64_t> hkey;
+      const int64_t* key = nullptr;
+      if ((rc = fetch(o.row_key, n, dev, hkey, &key))) return rc;
+      // pos[d] is now the end of domain d's rows
+      for (int d = 0; d < t; ++d)
+        std::stable_sort(perm_h.begin() + (pos[d] - dsize[d]), perm_h.begin() + pos[d],
+                         [key](int32_t a, int32_t b) { return key[a] < key[b]; });
+    }
     for (int64_t j = 0; j < n; ++j) iperm[perm_h[j]] = (int32_t)j;
     prp_h.resize(n + 1);
     pci_h.resize(nnz);

@@ -1,7 +1,8 @@
 // Host-side driver of the C ABI for the AddressSanitizer test
 // (tests/test_host_asan.py): the argument validation and the
-// domain-contiguous row permutation of ecg_setup run on the host before any
-// device call, so an instrumented build exercises them without a GPU.
+// domain-contiguous row permutation of ecg_setup (also by Morton keys) run
+// on the host before any device call, so an instrumented build exercises
+// them without a GPU.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -49,11 +50,22 @@ int main() {
     expect(ecg_setup(&c, n, rp.data(), ci.data(), v.data(), d3.data(), t, 2, &o), ECG_EINVAL, "domain range");
     ecg_opts o2 = o; o2.ca = 3;
     expect(ecg_setup(&c, n, rp.data(), ci.data(), v.data(), dom.data(), t, 2, &o2), ECG_EINVAL, "ca");
+    std::vector<int64_t> keys(n, 0);
+    ecg_opts o4 = o; o4.permute_domains = 0; o4.row_key = keys.data();
+    expect(ecg_setup(&c, n, rp.data(), ci.data(), v.data(), dom.data(), t, 2, &o4), ECG_EINVAL,
+           "row_key without the domain order");
+    expect(ecg_grid_morton_keys(nx, ny, 0, keys.data()), ECG_EINVAL, "morton nz0");
+    expect(ecg_grid_morton_keys(nx, ny, 1, nullptr), ECG_EINVAL, "morton null");
   }
-  // valid input in both row orders: host validation and the domain-contiguous
-  // permutation run; without a GPU the call then reports ECG_EDEVICE
-  for (int perm = 0; perm <= 1; ++perm) {
-    ecg_opts o3 = o; o3.permute_domains = perm;
+  // Morton keys of the grid (host code)
+  std::vector<int64_t> mkeys(n, -1);
+  expect(ecg_grid_morton_keys(nx, ny, 1, mkeys.data()), ECG_OK, "morton keys");
+  // valid input in both row orders and with Morton keys: host validation
+  // and the domain-contiguous permutation run; without a GPU the call then
+  // reports ECG_EDEVICE
+  for (int perm = 0; perm <= 2; ++perm) {
+    ecg_opts o3 = o; o3.permute_domains = perm > 0;
+    if (perm == 2) o3.row_key = mkeys.data();
     const int rc = ecg_setup(&c, n, rp.data(), ci.data(), v.data(), dom.data(), t, 2, &o3);
     if (rc == ECG_OK) ecg_destroy(c);
     else expect(rc, ECG_EDEVICE, "valid setup without a GPU");

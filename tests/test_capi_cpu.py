@@ -45,8 +45,8 @@ def test_opts_default():
     E.lib.ecg_opts_default(ctypes.byref(o))
     assert (o.variant, o.orth, o.precision, o.device_ptrs) == (0, 0, 0, 0)
     assert o.inner_tol == 1e-4 and o.max_restarts == 20 and o.grid == 0
-    assert list(o.reserved) == [0] * 3
-    assert o.ca == 0
+    assert list(o.reserved) == [0]
+    assert o.ca == 0 and o.row_key is None
     assert o.permute_domains == 1 and o.progress_every == 0
 
 
@@ -74,7 +74,7 @@ def small():
 @pytest.mark.parametrize("case", [
     "n0", "t0", "t65", "t_gt_n", "s0", "s17", "rowptr0", "decreasing", "col_range",
     "part_range", "empty_domain", "nan_value", "reserved", "variant", "inner_tol", "q_cap",
-    "ca"])
+    "ca", "row_key"])
 def test_setup_rejects(small, case):
     p, dom = small
     rp, ci, va, pd = p.rowptr.copy(), p.colind.copy(), p.vals.copy(), dom.copy()
@@ -105,7 +105,7 @@ def test_setup_rejects(small, case):
     elif case == "nan_value":
         va[10] = np.nan
     elif case == "reserved":
-        kw = {"reserved": (ctypes.c_int32 * 3)(0, 1, 0)}
+        kw = {"reserved": (ctypes.c_int32 * 1)(1)}
     elif case == "variant":
         kw = {"variant": 7}
     elif case == "inner_tol":
@@ -114,6 +114,9 @@ def test_setup_rejects(small, case):
         kw = {"variant": E.SRECG2, "q_cap_blocks": 1}
     elif case == "ca":
         kw = {"ca": 3}
+    elif case == "row_key":   # a key order needs the domain-contiguous order
+        keys = np.arange(p.n, dtype=np.int64)
+        kw = {"permute_domains": 0, "row_key": keys.ctypes.data}
     code, msg = _setup(n, rp, ci, va, pd, t, s, **kw)
     assert code == E.EINVAL, (case, code, msg)
     assert msg
@@ -146,3 +149,36 @@ def test_partition_rejects(args):
     buf = (ctypes.c_int32 * 4)()
     assert E.lib.ecg_partition_grid(*args, ctypes.addressof(buf), None) == E.EINVAL
     assert E.lib.ecg_partition_grid(4, 4, 1, 1, 1, 1, None, None) == E.EINVAL
+
+
+def _morton_reference(nx, ny, nz):
+    # bit b of x, y, z at bits 3b, 3b+1, 3b+2, written out bit by bit
+    keys = np.zeros(nx * ny * nz, dtype=np.int64)
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                key = 0
+                for b in range(21):
+                    key |= ((i >> b) & 1) << (3 * b)
+                    key |= ((j >> b) & 1) << (3 * b + 1)
+                    key |= ((k >> b) & 1) << (3 * b + 2)
+                keys[i + nx * (j + ny * k)] = key
+    return keys
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (5, 3, 7), (37, 1, 1), (12, 9, 1)])
+def test_grid_morton_keys(shape):
+    # host code: against the bit-by-bit definition; distinct keys, and on a
+    # power-of-two cube they are exactly 0 .. n-1 (a permutation)
+    keys = E.grid_morton_keys(shape)
+    assert np.array_equal(keys, _morton_reference(*shape))
+    assert np.unique(keys).size == keys.size
+    if shape == (8, 8, 8):
+        assert np.array_equal(np.sort(keys), np.arange(512))
+
+
+def test_grid_morton_keys_rejects():
+    keys = np.zeros(8, dtype=np.int64)
+    assert E.lib.ecg_grid_morton_keys(0, 2, 2, keys.ctypes.data) == E.EINVAL
+    assert E.lib.ecg_grid_morton_keys(2, 2, 2, None) == E.EINVAL
+    assert E.lib.ecg_grid_morton_keys(1 << 21, 1, 1, keys.ctypes.data) == E.EINVAL

@@ -5,6 +5,8 @@ benchmark uses (default grid, stream and options).
   the first s-step iteration is compared element by element with the
   oracle's (x_1 over all 2.1M rows; at 16 columns also the basis it built),
   in the FP64 and the mixed form.
+* 128^3 skyscraper with the rows of each domain in Morton order: the first
+  iterate against the oracle.
 * 128^3 anisotropic, CA SRE-CG: the first two iterates against the oracle.
 * 1000^2 log-uniform (t = 16, s = 3): x_1 and x_4 over all 1M rows and the
   residual history against the oracle's.
@@ -69,6 +71,22 @@ def test_skyscraper_first_iteration(E, sky, mixed):
         Vr, AVr = ref.extra["V"][0]
         assert np.abs(V - Vr).max() <= 1e-10 * np.abs(Vr).max()
         assert np.abs(AV - AVr).max() <= 1e-10 * np.abs(AVr).max()
+    sol.close()
+
+
+def test_skyscraper_first_iteration_morton_order(E, sky):
+    # the rows of each domain stored in Morton order (the grid's keys): the
+    # first iterate, in the caller's order, against the oracle's
+    p, A, dom = sky
+    ref = O.sstep_srecg(A, dom, p.t, p.s, p.b, tol=p.tol, maxit=1, record=True)
+    sol, _ = _device_solver(E, p, row_key=E.grid_morton_keys(p.shape))
+    x, info = sol.solve(p.b, tol=p.tol, maxit=1)
+    assert info.iters == 1
+    xr = ref.extra["xs"][1]
+    rel = float(np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr))
+    print(f"Morton order x_1 relative difference {rel:.2e}")
+    assert rel <= 1e-10
+    assert abs(info.hist[1] - ref.hist[1]) <= 1e-10 * ref.hist[1]
     sol.close()
 
 

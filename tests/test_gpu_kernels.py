@@ -93,6 +93,61 @@ def test_domain_order_bit_exact(E, shape, parts, t):
     sol0.close()
 
 
+def _morton(shape):
+    # Morton keys of a grid written out with numpy (bit b of x, y, z at bits
+    # 3b, 3b+1, 3b+2), independent of the library's
+    nx, ny, nz = shape
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    key = np.zeros(i.shape, dtype=np.int64)
+    for b in range(21):
+        for c, a in enumerate((i, j, k)):
+            key |= ((a.astype(np.int64) >> b) & 1) << (3 * b + c)
+    return key.ravel()
+
+
+@pytest.mark.parametrize("shape,parts,t", [((37, 29, 5), (5, 3, 2), 30),
+                                           ((256, 256, 256), (4, 4, 4), 64)])
+def test_keyed_domain_order_bit_exact(E, shape, parts, t):
+    # the row order by key within each domain against the oracle's: seeded
+    # keys from a small range (ties resolved by row) and the grid's Morton
+    # keys (the library's own keys equal an independent numpy form)
+    dom = O.partition_grid(shape, parts)
+    n = dom.shape[0]
+    rp, ci, va = np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n)
+    rng = np.random.default_rng(11)
+    mort = _morton(shape)
+    assert np.array_equal(E.grid_morton_keys(shape), mort)
+    for key in (rng.integers(0, 50, n).astype(np.int64), mort):
+        sol = E.Solver(rp, ci, va, dom, t, 1, row_key=key)
+        assert np.array_equal(sol.domain_order().cpu().numpy(), O.domain_order(dom, key))
+        sol.close()
+
+
+def test_morton_order_solve(E):
+    # a solve with the rows of each domain in Morton order: the same count
+    # and x within 1e-10 of the solve in the caller's order (a well-
+    # conditioned system), T(r) and SDDMM bit-exact in the caller's order
+    p = P.poisson2d(40, t=8, parts=(2, 4, 1))
+    A = p.scipy()
+    dom = O.partition_grid(p.shape, p.parts)
+    key = _morton(p.shape)
+    a = E.Solver(p.rowptr, p.colind, p.vals, dom, 8, 2, row_key=key)
+    b = E.Solver(p.rowptr, p.colind, p.vals, dom, 8, 2)
+    rng = np.random.default_rng(3)
+    r = rng.standard_normal(p.n)
+    assert np.array_equal(a.tsplit(r).cpu().numpy(), O.split_T(r, dom, 8))
+    lam, x = rng.standard_normal(p.n), rng.standard_normal(p.n)
+    assert np.array_equal(a.sddmm(lam, x).cpu().numpy(), O.sddmm(p.rowptr, p.colind, lam, x))
+    xa, ia = a.solve(p.b, tol=1e-10, maxit=2000)
+    xb, ib = b.solve(p.b, tol=1e-10, maxit=2000)
+    assert ia.status == ib.status == E.OK and ia.iters == ib.iters
+    xa, xb = xa.cpu().numpy(), xb.cpu().numpy()
+    assert np.linalg.norm(xa - xb) <= 1e-10 * np.linalg.norm(xb)
+    assert np.linalg.norm(p.b - A @ xa) <= 1e-10 * np.linalg.norm(p.b)
+    a.close()
+    b.close()
+
+
 def test_permuted_order_results_in_caller_order(E):
     # every entry point returns the caller's order: T(r) bit-exact, SDDMM
     # bit-exact, the product within rounding, and the solve within 1e-10

@@ -5,8 +5,10 @@ ecg_solver.hip is compiled with the sanitizer on its host side only (the
 device code is not instrumented) and linked with the kernels object of the
 normal build and a small C++ driver (tests/host_asan_driver.cpp).  The
 driver runs the argument validation of ecg_setup and, on valid input, the
-domain-contiguous row permutation in both row orders; both run before the
-first device call, so without a GPU setup then reports ECG_EDEVICE.  A
+domain-contiguous row permutation (the caller's order within a domain, and
+the Morton key order with the keys from ecg_grid_morton_keys); both run
+before the first device call, so without a GPU setup then reports
+ECG_EDEVICE.  A
 planted heap overflow, built the same way, must be reported, so that a
 clean run means something."""
 import os
