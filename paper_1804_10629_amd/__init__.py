@@ -249,6 +249,7 @@ class Solver:
         self.t, self.s = int(t), int(s)
         _check(lib.ecg_setup(ctypes.byref(self._ctx), self.n, rp.data_ptr(), ci.data_ptr(),
                              va.data_ptr(), pd.data_ptr(), self.t, self.s, ctypes.byref(o)))
+        o.row_key = None   # the library keeps its own order; the key tensor may go
         if precond_blocks is not None:
             self.set_preconditioner(PREC_BJ_IC0, precond_blocks)
 
