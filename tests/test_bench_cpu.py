@@ -41,6 +41,21 @@ def test_measured_traffic_only_for_the_current_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("cgs_gram", "skyscraper3d") is None
 
 
+def test_measured_traffic_per_row_order(tmp_path, monkeypatch):
+    # lines without a row order are the domain order's; another row order
+    # gets no traffic unless a line was measured with it
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    src = bench.kernel_source_hash()
+    dom = {"kclass": "spmm", "workload": "randomblocks3d", "kernel_source_sha256_16": src,
+           "hbm_gb_per_launch": 42.3, "file": "x"}
+    _write_profile(tmp_path, [dom])
+    assert bench.measured_traffic("spmm", "randomblocks3d")["hbm_gb_per_launch"] == 42.3
+    assert bench.measured_traffic("spmm", "randomblocks3d", row_order="morton") is None
+    _write_profile(tmp_path, [dom, dict(dom, row_order="morton", hbm_gb_per_launch=30.0)])
+    assert bench.measured_traffic("spmm", "randomblocks3d", "fp64", "morton")["hbm_gb_per_launch"] == 30.0
+    assert bench.measured_traffic("spmm", "randomblocks3d", "fp64", "domain")["hbm_gb_per_launch"] == 42.3
+
+
 def test_kernel_source_hash_is_the_kernel_file():
     import hashlib
     path = os.path.join(ROOT, "paper_1804_10629_amd", "csrc", "ecg_kernels.hip")
